@@ -1,0 +1,184 @@
+"""Benchmark: FP64 Zernike basis entries/s on the L = M = 50 polar-grid workload
+(1326 ANSI modes n <= 50 at 64 Chebyshev-Gauss-Lobatto radii x 128 theta =
+8192 points; outputs Z, dZ/dr, d2Z/dr2, d3Z/dr3, dZ/dtheta), plus the
+mixed-precision vs FP64 speedup of the Zernike series forward + backward.
+
+One step = one zp_basis call over the whole grid (inputs resident in HBM).
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def _parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-series", action="store_true")
+    ap.add_argument("--cpu-sample-points", type=int, default=0,
+                    help="points of the workload the oracle is timed on (0: auto, ~10-30 s)")
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, sample_points: int):
+    """The oracle (quad precision, OpenMP over points), untuned, on a bounded
+    sample of the same workload's points; scaled to entries/s."""
+    import oracle
+
+    oracle.build(force=False)
+    threads = oracle.max_threads()
+    if sample_points <= 0:
+        # calibrate on a few points, then aim for ~15 s
+        t0 = time.perf_counter()
+        k = max(threads, 16)
+        oracle.basis(wl.n, wl.m, wl.r[:k], wl.theta[:k], wl.mask)
+        dt = max(time.perf_counter() - t0, 1e-3)
+        sample_points = int(min(wl.P, max(k, 15.0 / dt * k)))
+    idx = np.linspace(0, wl.P - 1, sample_points).astype(np.int64)
+    t0 = time.perf_counter()
+    oracle.basis(wl.n, wl.m, wl.r[idx], wl.theta[idx], wl.mask)
+    dt = time.perf_counter() - t0
+    entries = wl.M * 5 * sample_points
+    return {"value": entries / dt, "unit": "entries/s", "cores": threads, "kind": "oracle",
+            "sample": f"{sample_points} of {wl.P} grid points (evenly strided), all {wl.M} modes, 5 outputs; "
+                      f"{dt:.1f} s"}
+
+
+def series_leg(steps: int, warmup: int):
+    """FP64 vs mixed-precision Zernike series forward + backward on the n <= 64
+    workload (2145 modes, 65536 disc points, 1024 coefficient sets); the
+    mixed results' error is measured against the FP64 results."""
+    import torch
+
+    import paper_2409_19156_amd as zp
+    import zp_workloads as W
+
+    wl = W.series_n64()
+    dev = torch.device("cuda:0")
+    r, th = torch.from_numpy(wl.r).to(dev), torch.from_numpy(wl.theta).to(dev)
+    c, g = torch.from_numpy(wl.c).to(dev), torch.from_numpy(wl.g).to(dev)
+    out, ref = {}, None
+    stream = torch.cuda.current_stream(dev)
+    for prec in ("fp64", "fp32", "bf16x3"):
+        full, _, cb = zp.series_sizes(wl.M, wl.P, wl.B, prec)
+        ws = torch.empty(full, dtype=torch.uint8, device=dev)
+        cache = torch.empty(cb, dtype=torch.uint8, device=dev)
+
+        def step():
+            f = zp.series_forward(wl.n, wl.m, r, th, c, prec, cache=cache, ws=ws)
+            return (f,) + zp.series_backward(wl.n, wl.m, r, th, c, g, prec, cache=cache, ws=ws)
+
+        for _ in range(warmup):
+            res = step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            res = step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        entry = {"ms_fwd_bwd": ms, "gemm_gflop": 3 * 2.0 * wl.P * wl.M * wl.B / 1e9}
+        entry["algorithmic_tflops"] = entry["gemm_gflop"] / ms
+        if prec == "fp64":
+            ref = [x.clone() for x in res]
+        else:
+            errs = [((a - b).abs().max() / b.abs().max()).item() for a, b in zip(res, ref)]
+            entry["rel_err_vs_fp64"] = dict(zip(("f", "grad_c", "grad_r", "grad_theta"), errs))
+        out[prec] = entry
+        del ws, cache
+        torch.cuda.empty_cache()
+    out["speedup_bf16x3_vs_fp64"] = out["fp64"]["ms_fwd_bwd"] / out["bf16x3"]["ms_fwd_bwd"]
+    out["speedup_fp32_vs_fp64"] = out["fp64"]["ms_fwd_bwd"] / out["fp32"]["ms_fwd_bwd"]
+    out["workload"] = "series_n64: ANSI n<=64 (2145 modes), 65536 disc points, 1024 sets, fwd+bwd (c, r, theta)"
+    return out
+
+
+def main():
+    args = _parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); multi-GPU runs are not part of this "
+              "build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2409_19156_amd as zp
+    import zp_workloads as W
+
+    wl = W.basis_L50()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    r = torch.from_numpy(wl.r).to(dev)
+    th = torch.from_numpy(wl.theta).to(dev)
+    out = torch.empty((5, wl.M, wl.P), dtype=torch.float64, device=dev)
+    entries = wl.M * wl.P * 5
+    bytes_per_launch = entries * 8 + wl.P * 16  # outputs written + r, theta read
+
+    t0 = time.perf_counter()
+    zp.basis(wl.n, wl.m, r, th, 31, out=out)
+    torch.cuda.synchronize()
+    first_call_ms = (time.perf_counter() - t0) * 1e3
+    for _ in range(args.warmup):
+        zp.basis(wl.n, wl.m, r, th, 31, out=out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        zp.basis(wl.n, wl.m, r, th, 31, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t_wall) * 1e3
+    ms = ev0.elapsed_time(ev1) / args.steps
+    value = entries / (ms * 1e-3)
+    achieved = bytes_per_launch / (ms * 1e-3) / 1e9
+
+    res = {
+        "metric": "Zernike basis entries/s FP64 (L=M=50) & series fwd+bwd speedup at stated err",
+        "value": value,
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "basis_L50: ANSI n<=50 (1326 modes) on 64 CGL radii x 128 theta (8192 points), "
+                               "outputs Z, dZ/dr, d2Z/dr2, d3Z/dr3, dZ/dtheta",
+                   "modes": wl.M, "points": wl.P, "outputs": 5, "entries": entries},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "chain_kernel<3,true>", "bytes_per_launch": bytes_per_launch,
+                     "avg_launch_us": ms * 1e3},
+        "first_call_ms": first_call_ms,
+        "timed_wall_ms": wall_ms,
+    }
+    if not args.no_series:
+        res["series"] = series_leg(steps=max(3, min(args.steps, 10)), warmup=2)
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_points)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,168 @@
+/*
+ * zp.h -- C ABI of libzp, the MI355X (gfx950) library for radial Zernike
+ * polynomials, the full Zernike basis and the differentiable Zernike series.
+ *
+ * Mathematics (ZERNIPAX paper, Sec. 2):
+ *   mode (n, m): n >= 0, |m| <= n, n - |m| even                 (Sec. 2)
+ *   R_n^{|m|}(r) = (-1)^K r^|m| P_K^{(|m|,0)}(1 - 2r^2), K = (n - |m|)/2
+ *                                                              (Eq. jacobi-relation)
+ *   Z_n^m(r, theta) = R_n^{|m|}(r) cos(m theta)       for m >= 0
+ *                   = R_n^{|m|}(r) sin(|m| theta)     for m < 0  (Eq. zernike-poly)
+ * Polynomials are unnormalised, as in the paper.
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named h_* are host memory, d_* are device memory.  The caller
+ *     owns every buffer; the library only reads inputs and writes outputs.
+ *   - Mode lists are host arrays (they are metadata, like shapes).  Duplicates
+ *     are allowed: every column is written, in order (the paper's duplicated-
+ *     mode use, Sec. 3 footnote).  n may not exceed ZP_N_MAX.
+ *   - Point arrays are FP64 device arrays.  r is meant to lie in [0, 1] and
+ *     theta in [0, 2 pi]; values outside are evaluated as polynomials /
+ *     trigonometric functions but accuracy is only guaranteed inside.  r is
+ *     not range-checked (that would need a device round trip); NaN in gives
+ *     NaN out.
+ *   - Output planes are laid out [plane][mode][point], point fastest, i.e.
+ *     each plane is the paper's (points x modes) output array in column-major
+ *     order (Algorithms 1 and 2, "Output").
+ *   - Every call is asynchronous on `stream` (a hipStream_t; NULL means the
+ *     default stream).  All argument validation happens on the host before
+ *     any device work: on error nothing is written and no kernel is launched.
+ *     M == 0 or P == 0 (or B == 0 for the series) is a successful no-op.
+ *   - The library allocates device memory only for its cached per-mode-list
+ *     tables ("plans"), which zp_cache_clear() releases.  Calls from several
+ *     host threads are safe; calls that write the same buffers race, as any
+ *     asynchronous work does.
+ */
+#ifndef ZP_H
+#define ZP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum zp_status {
+    ZP_OK = 0,
+    ZP_ERR_MODE = 1,      /* a mode has n < 0, |m| > n, n - |m| odd, or n > ZP_N_MAX */
+    ZP_ERR_ARG = 2,       /* null pointer with work to do, negative size, bad mask */
+    ZP_ERR_ORDER = 3,     /* derivative order outside 0..3 */
+    ZP_ERR_WORKSPACE = 4, /* workspace smaller than the minimum for this call */
+    ZP_ERR_HIP = 5,       /* a HIP runtime call or kernel launch failed */
+    ZP_ERR_PREC = 6       /* unknown zp_prec value */
+} zp_status;
+
+/* Contraction precision of the series (the basis itself is always evaluated
+ * in FP64). */
+typedef enum zp_prec {
+    ZP_FP64 = 0,  /* FP64 MFMA, FP64 accumulation */
+    ZP_FP32 = 1,  /* operands rounded to FP32, FP32 MFMA */
+    ZP_BF16X3 = 2 /* operands rounded to FP32 and split into three BF16 parts
+                     (hi + mid + lo), six BF16 MFMA cross products with FP32
+                     accumulation */
+} zp_prec;
+
+#define ZP_N_MAX 1000 /* largest radial order n accepted */
+
+/* Output selection bits of zp_basis. */
+#define ZP_Z 1u       /* Z                        */
+#define ZP_DR 2u      /* dZ/dr                    */
+#define ZP_DR2 4u     /* d2Z/dr2                  */
+#define ZP_DR3 8u     /* d3Z/dr3                  */
+#define ZP_DTHETA 16u /* dZ/dtheta                */
+
+/*
+ * zp_radial -- radial polynomials and their r-derivatives.
+ * Paper: Eq. (jacobi-relation) with the Jacobi recurrence Eq.
+ * (jacobi-recursion) / its beta = 0 form, and the derivative identity with
+ * the Pochhammer symbol (Sec. 2); one recurrence chain per |m| shared by all n
+ * (Algorithm 1).
+ *   h_n, h_m  host int32[M]: modes; the sign of m is ignored (R uses |m|)
+ *   d_r       device double[P]
+ *   max_dr    0..3: highest r-derivative computed
+ *   d_out     device double[(max_dr+1) * M * P]: plane j holds d^jR/dr^j,
+ *             element (j, i, p) at ((j*M + i)*P + p)
+ * Errors: ZP_ERR_MODE, ZP_ERR_ORDER, ZP_ERR_ARG (negative M or P, null
+ * pointer with M*P > 0), ZP_ERR_HIP.
+ */
+zp_status zp_radial(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r, int64_t P,
+                    int32_t max_dr, double *d_out, void *stream);
+
+/*
+ * zp_basis -- full Zernike basis and selected derivatives, Eq. (zernike-poly).
+ *   h_n, h_m  host int32[M]: modes; m >= 0 selects cos(m theta), m < 0
+ *             selects sin(|m| theta)
+ *   d_r, d_theta  device double[P]
+ *   mask      nonzero subset of ZP_Z | ZP_DR | ZP_DR2 | ZP_DR3 | ZP_DTHETA
+ *   d_out     device double[popcount(mask) * M * P]: the selected outputs in
+ *             increasing bit order, each a [M][P] plane.  dZ/dtheta is
+ *             -m R sin(m theta) for m >= 0 and |m| R cos(|m| theta) for m < 0.
+ * Errors: as zp_radial; ZP_ERR_ARG also for mask == 0 or bits above 4.
+ */
+zp_status zp_basis(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r,
+                   const double *d_theta, int64_t P, uint32_t mask, double *d_out, void *stream);
+
+/*
+ * Zernike series f(r_p, theta_p)_b = sum_k c[k][b] Z_k(r_p, theta_p) for B
+ * coefficient sets at once (the basis contracted with coefficients; the
+ * paper's use of Zernike polynomials as a spectral basis, Sec. 1 and 3), and
+ * its adjoint.  Layouts: c [M][B], f and g [P][B], all row-major FP64.
+ *
+ * Memory: the contraction needs a caller-provided device workspace d_ws of
+ * ws_bytes.  zp_series_workspace() reports the size that processes all P
+ * points in one pass; any smaller size down to the reported minimum is
+ * accepted and processes the points in chunks.  d_ws must be 256-byte
+ * aligned.  Its contents are scratch between calls.
+ *
+ * Basis cache: the forward can keep the basis for the backward in a
+ * caller-provided device buffer d_cache of zp_series_cache_bytes() bytes
+ * (opaque layout, depends on prec).  If the backward receives d_cache == NULL
+ * it recomputes the basis chunk by chunk instead (for when points x modes is
+ * too large to keep).  A cache is valid only for the same modes, points, and
+ * prec as the forward that filled it.
+ */
+zp_status zp_series_workspace(int64_t M, int64_t P, int64_t B, int32_t prec, size_t *full_bytes,
+                              size_t *min_bytes);
+zp_status zp_series_cache_bytes(int64_t M, int64_t P, int32_t prec, size_t *bytes);
+
+/*
+ * zp_series_fwd -- f = Z^T c (f [P][B] = sum over modes).
+ *   d_c       device double[M*B]
+ *   d_f       device double[P*B] (output)
+ *   d_cache   nullable device buffer of zp_series_cache_bytes(M, P, prec):
+ *             filled for a later zp_series_bwd
+ * Errors: as zp_basis, plus ZP_ERR_PREC and ZP_ERR_WORKSPACE.
+ */
+zp_status zp_series_fwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r,
+                        const double *d_theta, int64_t P, const double *d_c, int64_t B, int32_t prec,
+                        double *d_f, void *d_cache, void *d_ws, size_t ws_bytes, void *stream);
+
+/*
+ * zp_series_bwd -- adjoint of zp_series_fwd for an upstream gradient g = dL/df:
+ *   grad_c[k][b]    = sum_p Z_k(p) g[p][b]
+ *   grad_r[p]       = sum_b g[p][b] sum_k dZ_k/dr(p) c[k][b]
+ *   grad_theta[p]   = sum_b g[p][b] sum_k dZ_k/dtheta(p) c[k][b]
+ * Each of d_grad_c [M*B], d_grad_r [P], d_grad_theta [P] is nullable (not
+ * computed when NULL); results are overwritten, not accumulated.  Sums have
+ * a fixed order (no floating-point atomics): repeated calls are bitwise equal.
+ */
+zp_status zp_series_bwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r,
+                        const double *d_theta, int64_t P, const double *d_c, int64_t B, int32_t prec,
+                        const double *d_g, const void *d_cache, double *d_grad_c, double *d_grad_r,
+                        double *d_grad_theta, void *d_ws, size_t ws_bytes, void *stream);
+
+/* Static description of a status code. */
+const char *zp_status_string(zp_status s);
+/* Detail of the last error raised on the calling host thread ("" if none). */
+const char *zp_last_error(void);
+/* Release every cached plan (waits for the device first). */
+void zp_cache_clear(void);
+/* ABI version of this header: 1. */
+int32_t zp_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ZP_H */

@@ -1,0 +1,231 @@
+"""MI355X (gfx950) Zernike polynomials: radial part, full basis, and the
+differentiable Zernike series.
+
+Thin binding over libzp.so (C ABI in include/zp.h).  Torch supplies device
+memory and the current stream; every step of the computation runs in the
+library's HIP kernels.  There is no CPU fallback: without the built library or
+a GPU these functions raise.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import ZpError
+
+Z, DR, DR2, DR3, DTHETA = 1, 2, 4, 8, 16
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+
+__all__ = ["radial", "basis", "ZpError", "Z", "DR", "DR2", "DR3", "DTHETA", "PREC", "modes_i32"]
+
+
+def modes_i32(n, m):
+    """Host int32 copies of the mode arrays (they are metadata, like shapes)."""
+    if isinstance(n, torch.Tensor):
+        n = n.detach().cpu().numpy()
+    if isinstance(m, torch.Tensor):
+        m = m.detach().cpu().numpy()
+    n = np.ascontiguousarray(n, dtype=np.int32).reshape(-1)
+    m = np.ascontiguousarray(m, dtype=np.int32).reshape(-1)
+    if n.shape != m.shape:
+        raise ValueError("n and m must have the same length")
+    return n, m
+
+
+def _points(x: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if x.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    return x.reshape(-1).contiguous()
+
+
+def _stream(dev: torch.device) -> int:
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def radial(n, m, r: torch.Tensor, max_dr: int = 0, out: torch.Tensor | None = None) -> torch.Tensor:
+    """d^j R_n^{|m|}(r) / dr^j for j = 0..max_dr.
+
+    Returns a float64 tensor [max_dr+1, M, P] on r's device (plane j, mode i,
+    point p).  ``out[j].T`` is the paper's (points x modes) array."""
+    lib = _lib.load()
+    nh, mh = modes_i32(n, m)
+    r = _points(r, "r")
+    M, P = nh.size, r.numel()
+    if out is None:
+        out = torch.empty((max_dr + 1, M, P), dtype=torch.float64, device=r.device)
+    elif out.shape != (max_dr + 1, M, P) or out.dtype != torch.float64 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 tensor [max_dr+1, M, P]")
+    with torch.cuda.device(r.device):
+        st = lib.zp_radial(nh.ctypes.data, mh.ctypes.data, M, r.data_ptr(), P, int(max_dr), out.data_ptr(),
+                           _stream(r.device))
+    _lib.check(st, "zp_radial")
+    return out
+
+
+def basis(n, m, r: torch.Tensor, theta: torch.Tensor, mask: int = Z, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Z_n^m(r, theta) and the derivatives selected by ``mask`` (Z, DR, DR2,
+    DR3, DTHETA bits).  Returns float64 [popcount(mask), M, P]."""
+    lib = _lib.load()
+    nh, mh = modes_i32(n, m)
+    r = _points(r, "r")
+    theta = _points(theta, "theta")
+    if theta.numel() != r.numel():
+        raise ValueError("r and theta must have the same number of points")
+    M, P = nh.size, r.numel()
+    nout = bin(int(mask) & 31).count("1")
+    shape = (max(nout, 1), M, P)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=r.device)
+    elif out.shape != shape or out.dtype != torch.float64 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 tensor [popcount(mask), M, P]")
+    with torch.cuda.device(r.device):
+        st = lib.zp_basis(nh.ctypes.data, mh.ctypes.data, M, r.data_ptr(), theta.data_ptr(), P, int(mask),
+                          out.data_ptr(), _stream(r.device))
+    _lib.check(st, "zp_basis")
+    return out
+
+
+# ------------------------------------------------------------------ series --
+
+def _prec_code(prec) -> int:
+    if isinstance(prec, str):
+        if prec not in PREC:
+            raise ValueError(f"prec must be one of {sorted(PREC)}")
+        return PREC[prec]
+    return int(prec)
+
+
+def series_sizes(M: int, P: int, B: int, prec="fp64"):
+    """(workspace bytes for one pass, minimum workspace bytes, basis-cache bytes)."""
+    import ctypes
+
+    lib = _lib.load()
+    full = ctypes.c_size_t()
+    mn = ctypes.c_size_t()
+    cb = ctypes.c_size_t()
+    _lib.check(lib.zp_series_workspace(M, P, B, _prec_code(prec), ctypes.byref(full), ctypes.byref(mn)),
+               "zp_series_workspace")
+    _lib.check(lib.zp_series_cache_bytes(M, P, _prec_code(prec), ctypes.byref(cb)), "zp_series_cache_bytes")
+    return full.value, mn.value, cb.value
+
+
+def _budget(mem_budget):
+    import os
+
+    if mem_budget is not None:
+        return int(mem_budget)
+    return int(os.environ.get("ZP_MEM_BUDGET_BYTES", str(32 << 30)))
+
+
+def _workspace(M, P, B, prec, budget, device):
+    full, mn, _ = series_sizes(M, P, B, prec)
+    nbytes = full if full <= budget else max(mn, budget)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def _coef(c: torch.Tensor, M: int) -> torch.Tensor:
+    if not isinstance(c, torch.Tensor) or not c.is_cuda or c.dtype != torch.float64:
+        raise TypeError("c must be a float64 GPU tensor [M, B]")
+    if c.dim() != 2 or c.shape[0] != M:
+        raise ValueError(f"c must have shape [M={M}, B]")
+    return c.contiguous()
+
+
+def series_forward(n, m, r, theta, c, prec="fp64", cache: torch.Tensor | None = None,
+                   ws: torch.Tensor | None = None, mem_budget=None) -> torch.Tensor:
+    """f[p, b] = sum_k c[k, b] Z_k(r_p, theta_p).  If ``cache`` (uint8, from
+    ``series_sizes``) is given, the basis is kept in it for ``series_backward``."""
+    lib = _lib.load()
+    nh, mh = modes_i32(n, m)
+    r, theta = _points(r, "r"), _points(theta, "theta")
+    M, P = nh.size, r.numel()
+    c = _coef(c, M)
+    B = c.shape[1]
+    f = torch.empty((P, B), dtype=torch.float64, device=r.device)
+    if ws is None:
+        ws = _workspace(M, P, B, prec, _budget(mem_budget), r.device)
+    with torch.cuda.device(r.device):
+        st = lib.zp_series_fwd(nh.ctypes.data, mh.ctypes.data, M, r.data_ptr(), theta.data_ptr(), P, c.data_ptr(), B,
+                               _prec_code(prec), f.data_ptr(), cache.data_ptr() if cache is not None else None,
+                               ws.data_ptr(), ws.numel(), _stream(r.device))
+    _lib.check(st, "zp_series_fwd")
+    return f
+
+
+def series_backward(n, m, r, theta, c, g, prec="fp64", cache: torch.Tensor | None = None,
+                    need=(True, True, True), ws: torch.Tensor | None = None, mem_budget=None):
+    """(dL/dc, dL/dr, dL/dtheta) for upstream gradient g = dL/df [P, B]; entries
+    not in ``need`` are returned as None."""
+    lib = _lib.load()
+    nh, mh = modes_i32(n, m)
+    r, theta = _points(r, "r"), _points(theta, "theta")
+    M, P = nh.size, r.numel()
+    c = _coef(c, M)
+    B = c.shape[1]
+    g = g.contiguous()
+    if g.shape != (P, B) or g.dtype != torch.float64:
+        raise ValueError("g must be float64 [P, B]")
+    dev = r.device
+    gc = torch.empty((M, B), dtype=torch.float64, device=dev) if need[0] else None
+    gr = torch.empty(P, dtype=torch.float64, device=dev) if need[1] else None
+    gt = torch.empty(P, dtype=torch.float64, device=dev) if need[2] else None
+    if M == 0 or P == 0 or B == 0:
+        return tuple(None if x is None else x.zero_() for x in (gc, gr, gt))
+    if ws is None:
+        ws = _workspace(M, P, B, prec, _budget(mem_budget), dev)
+    ptr = (lambda t: t.data_ptr() if t is not None else None)
+    with torch.cuda.device(dev):
+        st = lib.zp_series_bwd(nh.ctypes.data, mh.ctypes.data, M, r.data_ptr(), theta.data_ptr(), P, c.data_ptr(), B,
+                               _prec_code(prec), g.data_ptr(), ptr(cache), ptr(gc), ptr(gr), ptr(gt), ws.data_ptr(),
+                               ws.numel(), _stream(dev))
+    _lib.check(st, "zp_series_bwd")
+    return gc, gr, gt
+
+
+class ZernikeSeries(torch.autograd.Function):
+    """f = Z(r, theta)^T c with a hand-written adjoint (zp_series_bwd).
+
+    The basis (Z, dZ/dr, dZ/dtheta) is kept from the forward when its size is
+    within the memory budget, and recomputed chunk by chunk in the backward
+    otherwise."""
+
+    @staticmethod
+    def forward(ctx, c, r, theta, n, m, prec="fp64", mem_budget=None):
+        nh, mh = modes_i32(n, m)
+        M, P, B = nh.size, r.numel(), c.shape[1]
+        budget = _budget(mem_budget)
+        _, _, cache_bytes = series_sizes(M, P, B, prec)
+        cache = None
+        if M and P and B and cache_bytes <= budget:
+            cache = torch.empty(cache_bytes, dtype=torch.uint8, device=r.device)
+        f = series_forward(nh, mh, r, theta, c, prec, cache=cache, mem_budget=budget)
+        ctx.modes = (nh, mh)
+        ctx.prec = prec
+        ctx.budget = budget
+        ctx.cache = cache
+        ctx.save_for_backward(c, r, theta)
+        return f
+
+    @staticmethod
+    def backward(ctx, g):
+        c, r, theta = ctx.saved_tensors
+        nh, mh = ctx.modes
+        need = ctx.needs_input_grad[:3]
+        gc, gr, gt = series_backward(nh, mh, r, theta, c, g, ctx.prec, cache=ctx.cache, need=need,
+                                     mem_budget=ctx.budget)
+        if gr is not None:
+            gr = gr.view_as(r)
+        if gt is not None:
+            gt = gt.view_as(theta)
+        return gc, gr, gt, None, None, None, None
+
+
+def series(c, r, theta, n, m, prec="fp64", mem_budget=None):
+    """Differentiable Zernike series f[p, b] = sum_k c[k, b] Z_k(r_p, theta_p)."""
+    return ZernikeSeries.apply(c, r, theta, n, m, prec, mem_budget)
+
+
+__all__ += ["series_sizes", "series_forward", "series_backward", "ZernikeSeries", "series"]

@@ -1,0 +1,530 @@
+// MFMA contractions for the Zernike series on gfx950, plus the small
+// conversion and fixed-order reduction kernels around them.
+//
+// C(i,j) = sum_k A(i,k) B(k,j) with a 256-thread workgroup (2 x 2 waves) per
+// BM x BN output tile.  Operands come from zero-padded buffers (every
+// dimension a multiple of kPad), so tile loads need no bounds checks; stores
+// are masked to the true output size.  Each operand tile is copied into LDS
+// in its global layout (k-contiguous rows, or rows along the other index),
+// with padding chosen so that the MFMA fragment reads are free of bank
+// conflicts; the fragment reads follow the layout.  The bf16 path needs
+// eight consecutive k per lane, so an operand that is not k-contiguous in
+// memory is transposed while it is written to LDS.  Tiles are double
+// buffered: the next tile's global loads are in flight during the current
+// tile's MFMAs.
+//
+// Element types:
+//   F64 : v_mfma_f64_16x16x4 (FP64 in, FP64 accumulate)
+//   F32 : v_mfma_f32_16x16x4 (FP32 in, FP32 accumulate)
+//   BF3 : value = hi + mid + lo (three bf16 planes); six v_mfma_f32_16x16x32_bf16
+//         cross products (hi.hi, hi.mid, mid.hi, hi.lo, mid.mid, lo.hi; the
+//         three dropped products are below 2^-24 relative)
+// The FP32-accumulating types add their FP32 accumulators into FP64 ones
+// every kFlush k and restart them, so FP32 rounding acts on partial sums of
+// at most kFlush terms.
+//
+// MFMA lane layouts (16x16 blocks): lane l supplies A[l%16][k] and B[k][l%16]
+// for k = l/16 (x4 shapes) or k = 8(l/16)..8(l/16)+7 (bf16 x32 shape); it
+// receives D[4(l/16)+t][l%16], t = 0..3.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "series.hpp"
+
+namespace zp {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;
+constexpr int kFlush = 128;
+
+template <int CT> struct CTr;
+template <> struct CTr<CT_F64> {
+    using T = double;
+    static constexpr int NP = 1, PK = 2;
+};
+template <> struct CTr<CT_F32> {
+    using T = float;
+    static constexpr int NP = 1, PK = 4;
+};
+template <> struct CTr<CT_BF3> {
+    using T = uint16_t;
+    static constexpr int NP = 3, PK = 8;
+};
+
+// LDS geometry of one operand tile (X rows of the output index by BK).
+template <int CT, int X, int BK, bool KC> struct Tile {
+    using T = typename CTr<CT>::T;
+    static constexpr bool ROWS_X = KC || CT == CT_BF3; // LDS [X][BK+PK], else [BK][X+16]
+    static constexpr int STRIDE = ROWS_X ? BK + CTr<CT>::PK : X + 16;
+    static constexpr int ELEMS = (ROWS_X ? X : BK) * STRIDE;
+    static constexpr int VEC = 16 / (int)sizeof(T);
+    static constexpr int GROWS = KC ? X : BK; // global tile rows
+    static constexpr int GCOLS = KC ? BK : X; // global tile contiguous columns
+    static constexpr int NV = GROWS * GCOLS / VEC;
+    static constexpr int PER = NV / kThreads;
+    static_assert(NV % kThreads == 0, "tile not divisible among threads");
+
+    using Regs = u4[PER][CTr<CT>::NP];
+
+    // Global -> registers for the tile whose output-index origin is x0 and k origin k0.
+    static __device__ __forceinline__ void load(Regs &reg, const T *base, int64_t ld, int64_t sub, int64_t x0,
+                                                int64_t k0)
+    {
+#pragma unroll
+        for (int v = 0; v < PER; ++v) {
+            const int idx = v * kThreads + (int)threadIdx.x;
+            const int gr = idx / (GCOLS / VEC);
+            const int gc = (idx % (GCOLS / VEC)) * VEC;
+            const int64_t off = KC ? (x0 + gr) * ld + (k0 + gc) : (k0 + gr) * ld + (x0 + gc);
+#pragma unroll
+            for (int p = 0; p < CTr<CT>::NP; ++p) reg[v][p] = *(const u4 *)(base + off + p * sub);
+        }
+    }
+
+    // Registers -> LDS buffer lds[NP][ELEMS].
+    static __device__ __forceinline__ void store(const Regs &reg, T *lds)
+    {
+#pragma unroll
+        for (int v = 0; v < PER; ++v) {
+            const int idx = v * kThreads + (int)threadIdx.x;
+            const int gr = idx / (GCOLS / VEC);
+            const int gc = (idx % (GCOLS / VEC)) * VEC;
+#pragma unroll
+            for (int p = 0; p < CTr<CT>::NP; ++p) {
+                T *L = lds + p * ELEMS;
+                if (KC || !ROWS_X) {
+                    *(u4 *)(L + gr * STRIDE + gc) = reg[v][p];
+                } else { // bf16 operand contiguous along x: transpose into [x][k]
+                    const u4 w = reg[v][p];
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q)
+                        L[(gc + q) * STRIDE + gr] = (T)((q & 1) ? (w[q >> 1] >> 16) : (w[q >> 1] & 0xFFFFu));
+                }
+            }
+        }
+    }
+};
+
+// Fragment read for the x4 shapes: element (x, k) of an LDS tile.
+template <class TL>
+__device__ __forceinline__ typename TL::T frag1(const typename TL::T *L, int x, int k)
+{
+    return TL::ROWS_X ? L[x * TL::STRIDE + k] : L[k * TL::STRIDE + x];
+}
+
+template <int CT, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, int EPI>
+__global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc g)
+{
+    using TR = CTr<CT>;
+    using T = typename TR::T;
+    using TA = Tile<CT, BM, BK, AKC>;
+    using TB = Tile<CT, BN, BK, BKC>;
+    constexpr int NP = TR::NP;
+    constexpr int FM = WM / 16, FN = WN / 16;
+    constexpr bool MIXED = CT != CT_F64;
+    static_assert((BM / WM) * (BN / WN) == 4, "four waves per workgroup");
+
+    __shared__ __attribute__((aligned(16))) T As[2][NP * TA::ELEMS];
+    __shared__ __attribute__((aligned(16))) T Bs[2][NP * TB::ELEMS];
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wm0 = (wave % (BM / WM)) * WM;
+    const int wn0 = (wave / (BM / WM)) * WN;
+    const int64_t i0 = (int64_t)blockIdx.x * BM;
+    const int64_t j0 = (int64_t)blockIdx.y * BN;
+
+    // k range of this workgroup (split-K along blockIdx.z)
+    const int64_t kchunk = g.K / g.splits;
+    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+    const int64_t kend = kbeg + kchunk;
+    const int ntiles = (int)((kend - kbeg) / BK);
+
+    using Acc = typename std::conditional<CT == CT_F64, d4, f4>::type;
+    Acc acc[FM][FN];
+    double acc64[MIXED ? FM : 1][MIXED ? FN : 1][4];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+            acc[a][b] = Acc{0, 0, 0, 0};
+            if (MIXED)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc64[MIXED ? a : 0][MIXED ? b : 0][t] = 0.0;
+        }
+
+    auto flush = [&]() {
+        if (MIXED) {
+#pragma unroll
+            for (int a = 0; a < FM; ++a)
+#pragma unroll
+                for (int b = 0; b < FN; ++b) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) acc64[MIXED ? a : 0][MIXED ? b : 0][t] += (double)acc[a][b][t];
+                    acc[a][b] = Acc{0, 0, 0, 0};
+                }
+        }
+    };
+
+    const T *a_base = (const T *)g.a.base;
+    const T *b_base = (const T *)g.b.base;
+    const int64_t a_ld = g.a.ld, a_sub = g.a.sub, b_ld = g.b.ld, b_sub = g.b.sub;
+    typename TA::Regs ra;
+    typename TB::Regs rb;
+    if (ntiles > 0) {
+        TA::load(ra, a_base, a_ld, a_sub, i0, kbeg);
+        TB::load(rb, b_base, b_ld, b_sub, j0, kbeg);
+        TA::store(ra, As[0]);
+        TB::store(rb, Bs[0]);
+    }
+    __syncthreads();
+
+    const int lx = lane & 15, lk = lane >> 4;
+    for (int t = 0; t < ntiles; ++t) {
+        const int cur = t & 1;
+        const bool more = t + 1 < ntiles;
+        if (more) {
+            TA::load(ra, a_base, a_ld, a_sub, i0, kbeg + (int64_t)(t + 1) * BK);
+            TB::load(rb, b_base, b_ld, b_sub, j0, kbeg + (int64_t)(t + 1) * BK);
+        }
+        const T *LA = As[cur];
+        const T *LB = Bs[cur];
+        if constexpr (CT == CT_BF3) {
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 32) {
+                bf8 fa[FM][3], fb[FN][3];
+#pragma unroll
+                for (int a = 0; a < FM; ++a)
+#pragma unroll
+                    for (int p = 0; p < 3; ++p)
+                        fa[a][p] = *(const bf8 *)(LA + p * TA::ELEMS + (wm0 + a * 16 + lx) * TA::STRIDE + kk + 8 * lk);
+#pragma unroll
+                for (int b = 0; b < FN; ++b)
+#pragma unroll
+                    for (int p = 0; p < 3; ++p)
+                        fb[b][p] = *(const bf8 *)(LB + p * TB::ELEMS + (wn0 + b * 16 + lx) * TB::STRIDE + kk + 8 * lk);
+#pragma unroll
+                for (int a = 0; a < FM; ++a)
+#pragma unroll
+                    for (int b = 0; b < FN; ++b) {
+                        // small cross products first, the leading one last
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][2], fb[b][0], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][1], fb[b][1], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][0], fb[b][2], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][1], fb[b][0], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][0], fb[b][1], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][0], fb[b][0], acc[a][b], 0, 0, 0);
+                    }
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 4) {
+                T fa[FM], fb[FN];
+#pragma unroll
+                for (int a = 0; a < FM; ++a) fa[a] = frag1<TA>(LA, wm0 + a * 16 + lx, kk + lk);
+#pragma unroll
+                for (int b = 0; b < FN; ++b) fb[b] = frag1<TB>(LB, wn0 + b * 16 + lx, kk + lk);
+#pragma unroll
+                for (int a = 0; a < FM; ++a)
+#pragma unroll
+                    for (int b = 0; b < FN; ++b) {
+                        if constexpr (CT == CT_F64)
+                            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+                        else
+                            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a], fb[b], acc[a][b], 0, 0, 0);
+                    }
+            }
+        }
+        if (MIXED && ((t + 1) * BK) % kFlush == 0) flush();
+        if (more) {
+            TA::store(ra, As[cur ^ 1]);
+            TB::store(rb, Bs[cur ^ 1]);
+        }
+        __syncthreads();
+    }
+    flush();
+
+    auto value = [&](int a, int b, int t) -> double {
+        if constexpr (MIXED)
+            return acc64[a][b][t];
+        else
+            return acc[a][b][t];
+    };
+
+    if constexpr (EPI == EPI_STORE || EPI == EPI_PARTIAL) {
+        double *C = g.C + (EPI == EPI_PARTIAL ? (int64_t)blockIdx.z * g.M * g.ldc : 0);
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+            for (int b = 0; b < FN; ++b) {
+                const int64_t j = j0 + wn0 + b * 16 + lx;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int64_t i = i0 + wm0 + a * 16 + 4 * lk + t;
+                    if (i < g.M && j < g.N) C[i * g.ldc + j] = value(a, b, t);
+                }
+            }
+    } else { // EPI_ROWDOT
+        constexpr int WCOLS = BN / WN;
+        __shared__ double red[2][WCOLS][BM];
+        const int wcol = wave / (BM / WM);
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int il = wm0 + a * 16 + 4 * lk + t;
+                const int64_t i = i0 + il;
+                double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+                for (int b = 0; b < FN; ++b) {
+                    const int64_t j = j0 + wn0 + b * 16 + lx;
+                    if (i < g.M && j < g.N) {
+                        const int64_t o = j * g.ldd + i;
+                        const double d1 = g.d_f32 ? (double)((const float *)g.D1)[o] : ((const double *)g.D1)[o];
+                        const double d2 = g.d_f32 ? (double)((const float *)g.D2)[o] : ((const double *)g.D2)[o];
+                        const double h = value(a, b, t);
+                        s1 = __builtin_fma(h, d1, s1);
+                        s2 = __builtin_fma(h, d2, s2);
+                    }
+                }
+#pragma unroll
+                for (int m = 1; m < 16; m <<= 1) {
+                    s1 += __shfl_xor(s1, m);
+                    s2 += __shfl_xor(s2, m);
+                }
+                if (lx == 0) {
+                    red[0][wcol][il] = s1;
+                    red[1][wcol][il] = s2;
+                }
+            }
+        __syncthreads();
+        for (int e = threadIdx.x; e < 2 * BM; e += kThreads) {
+            const int o = e / BM, il = e % BM;
+            const int64_t i = i0 + il;
+            if (i >= g.M) continue;
+            double s = 0.0;
+#pragma unroll
+            for (int c = 0; c < WCOLS; ++c) s += red[o][c][il];
+            g.part[((int64_t)blockIdx.y * 2 + o) * g.M + i] = s;
+        }
+    }
+}
+
+// Tile configurations.
+template <int CT> struct Cfg;
+template <> struct Cfg<CT_F64> {
+    static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32;
+};
+template <> struct Cfg<CT_F32> {
+    static constexpr int BM = 64, BN = 64, BK = 32, WM = 32, WN = 32;
+};
+template <> struct Cfg<CT_BF3> {
+    static constexpr int BM = 64, BN = 64, BK = 32, WM = 32, WN = 32;
+};
+
+template <int CT, bool AKC, bool BKC, int EPI>
+hipError_t launch_t(const GemmDesc &g, hipStream_t s)
+{
+    using C = Cfg<CT>;
+    const dim3 grid((unsigned)((g.M + C::BM - 1) / C::BM), (unsigned)((g.N + C::BN - 1) / C::BN),
+                    (unsigned)g.splits);
+    hipLaunchKernelGGL((gemm_kernel<CT, C::BM, C::BN, C::BK, C::WM, C::WN, AKC, BKC, EPI>), grid, dim3(kThreads), 0,
+                       s, g);
+    return hipGetLastError();
+}
+
+template <int CT, int EPI>
+hipError_t launch_e(const GemmDesc &g, hipStream_t s)
+{
+    if (g.a.kc && g.b.kc) return launch_t<CT, true, true, EPI>(g, s);
+    if (g.a.kc && !g.b.kc) return launch_t<CT, true, false, EPI>(g, s);
+    if (!g.a.kc && g.b.kc) return launch_t<CT, false, true, EPI>(g, s);
+    return launch_t<CT, false, false, EPI>(g, s);
+}
+
+template <int CT>
+hipError_t launch_c(const GemmDesc &g, hipStream_t s)
+{
+    switch (g.epi) {
+    case EPI_STORE: return launch_e<CT, EPI_STORE>(g, s);
+    case EPI_PARTIAL: return launch_e<CT, EPI_PARTIAL>(g, s);
+    default: return launch_e<CT, EPI_ROWDOT>(g, s);
+    }
+}
+
+// ------------------------------------------------------------ helpers --
+
+__device__ __forceinline__ uint16_t bf16_rne(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ double bf16_val(uint16_t h) { return (double)__uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ void put(void *dst, int ct, int64_t idx, int64_t sub, double v)
+{
+    if (ct == CT_F64) {
+        ((double *)dst)[idx] = v;
+    } else if (ct == CT_F32) {
+        ((float *)dst)[idx] = (float)v;
+    } else {
+        uint16_t *b = (uint16_t *)dst;
+        const uint16_t h = bf16_rne((float)v);
+        const double r1 = v - bf16_val(h);
+        const uint16_t m = bf16_rne((float)r1);
+        const double r2 = r1 - bf16_val(m);
+        b[idx] = h;
+        b[idx + sub] = m;
+        b[idx + 2 * sub] = bf16_rne((float)r2);
+    }
+}
+
+// Direct conversion: dst[r][c] for r < rows_pad, c < ldd.
+__global__ void convert_kernel(const double *__restrict__ src, int64_t R, int64_t C, int64_t lds, int ct, void *dst,
+                               int64_t ldd, int64_t rows_pad, int64_t sub)
+{
+    const int64_t total = rows_pad * ldd;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / ldd, c = e % ldd;
+        const double v = (r < R && c < C) ? src[r * lds + c] : 0.0;
+        put(dst, ct, e, sub, v);
+    }
+}
+
+// Transposing conversion through a 32 x 32 LDS tile: dst[c][r] = src[r][c],
+// dst is [rows_pad][ldd] with rows indexed by c.
+__global__ __launch_bounds__(256) void convert_t_kernel(const double *__restrict__ src, int64_t R, int64_t C,
+                                                        int64_t lds, int ct, void *dst, int64_t ldd, int64_t sub)
+{
+    __shared__ double tile[32][33];
+    const int64_t r0 = (int64_t)blockIdx.x * 32; // src rows = dst columns
+    const int64_t c0 = (int64_t)blockIdx.y * 32; // src cols = dst rows
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int y = ty; y < 32; y += 8) {
+        const int64_t r = r0 + y, c = c0 + tx;
+        tile[y][tx] = (r < R && c < C) ? src[r * lds + c] : 0.0;
+    }
+    __syncthreads();
+    for (int y = ty; y < 32; y += 8) {
+        const int64_t c = c0 + y, r = r0 + tx; // dst row c, column r
+        put(dst, ct, c * ldd + r, sub, tile[tx][y]);
+    }
+}
+
+__global__ void zero_kernel(void *dst, int ct, int64_t row0, int64_t rows, int64_t col0, int64_t cols, int64_t ld,
+                            int64_t sub)
+{
+    const int64_t total = rows * cols;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t idx = (row0 + e / cols) * ld + col0 + e % cols;
+        put(dst, ct, idx, sub, 0.0);
+    }
+}
+
+__global__ void splitk_reduce_kernel(const double *__restrict__ part, int S, int64_t M, int64_t N, double *C,
+                                     int64_t ldc, int accumulate)
+{
+    const int64_t total = M * N;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / N, j = e % N;
+        double s = 0.0;
+        for (int k = 0; k < S; ++k) s += part[(int64_t)k * M * ldc + i * ldc + j];
+        double *c = C + i * ldc + j;
+        *c = accumulate ? *c + s : s;
+    }
+}
+
+__global__ void rowdot_reduce_kernel(const double *__restrict__ part, int T, int64_t P, double *out1, double *out2)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    double s1 = 0.0, s2 = 0.0;
+    for (int t = 0; t < T; ++t) {
+        s1 += part[((int64_t)t * 2 + 0) * P + p];
+        s2 += part[((int64_t)t * 2 + 1) * P + p];
+    }
+    if (out1) out1[p] = s1;
+    if (out2) out2[p] = s2;
+}
+
+unsigned grid_for(int64_t total, int block)
+{
+    const int64_t g = (total + block - 1) / block;
+    return (unsigned)(g < 65536 * 4 ? (g < 1 ? 1 : g) : 65536 * 4);
+}
+
+} // namespace
+
+int rowdot_bn(int ct)
+{
+    return ct == CT_F64 ? Cfg<CT_F64>::BN : ct == CT_F32 ? Cfg<CT_F32>::BN : Cfg<CT_BF3>::BN;
+}
+
+zp_status launch_gemm(const GemmDesc &g, hipStream_t s)
+{
+    if (g.M <= 0 || g.N <= 0) return ZP_OK;
+    if (g.K % kPad != 0 || g.splits < 1 || (g.K / g.splits) % kPad != 0 || g.K / g.splits * g.splits != g.K)
+        return set_error(ZP_ERR_ARG, "internal: GEMM K split is not a multiple of the pad");
+    hipError_t e;
+    switch (g.ct) {
+    case CT_F64: e = launch_c<CT_F64>(g, s); break;
+    case CT_F32: e = launch_c<CT_F32>(g, s); break;
+    default: e = launch_c<CT_BF3>(g, s); break;
+    }
+    return hip_check(e, "gemm launch");
+}
+
+zp_status launch_convert(const double *src, int64_t R, int64_t C, int64_t lds, int ct, void *dst, int64_t ldd,
+                         int64_t rows_pad, int64_t sub, bool transpose, hipStream_t s)
+{
+    if (!transpose) {
+        hipLaunchKernelGGL(convert_kernel, dim3(grid_for(rows_pad * ldd, 256)), dim3(256), 0, s, src, R, C, lds, ct,
+                           dst, ldd, rows_pad, sub);
+    } else {
+        // dst is [rows_pad (>= C, padded)][ldd (>= R, padded)]; both multiples of 32
+        const dim3 grid((unsigned)(ldd / 32), (unsigned)(rows_pad / 32));
+        hipLaunchKernelGGL(convert_t_kernel, grid, dim3(256), 0, s, src, R, C, lds, ct, dst, ldd, sub);
+    }
+    return hip_check(hipGetLastError(), "convert launch");
+}
+
+zp_status launch_zero_pad(void *dst, int ct, int64_t rows, int64_t cols, int64_t rows_pad, int64_t ld, int64_t sub,
+                          hipStream_t s)
+{
+    if (rows_pad > rows) {
+        const int64_t n = (rows_pad - rows) * ld;
+        hipLaunchKernelGGL(zero_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, dst, ct, rows, rows_pad - rows,
+                           (int64_t)0, ld, ld, sub);
+    }
+    if (ld > cols && rows > 0) {
+        const int64_t n = rows * (ld - cols);
+        hipLaunchKernelGGL(zero_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, dst, ct, (int64_t)0, rows, cols,
+                           ld - cols, ld, sub);
+    }
+    return hip_check(hipGetLastError(), "zero-pad launch");
+}
+
+zp_status launch_splitk_reduce(const double *part, int S, int64_t M, int64_t N, double *C, int64_t ldc,
+                               bool accumulate, hipStream_t s)
+{
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid_for(M * N, 256)), dim3(256), 0, s, part, S, M, N, C, ldc,
+                       accumulate ? 1 : 0);
+    return hip_check(hipGetLastError(), "split-K reduce launch");
+}
+
+zp_status launch_rowdot_reduce(const double *part, int T, int64_t P, double *out1, double *out2, hipStream_t s)
+{
+    hipLaunchKernelGGL(rowdot_reduce_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, part, T, P, out1,
+                       out2);
+    return hip_check(hipGetLastError(), "row-dot reduce launch");
+}
+
+} // namespace zp

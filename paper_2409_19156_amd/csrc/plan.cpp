@@ -1,0 +1,185 @@
+// Host-side plans: mode validation, grouping of modes into one recurrence
+// chain per alpha = |m| (Algorithm 1 of the paper: a chain serves every n of
+// its alpha), per-step coefficients, and a small device-side cache.
+#include <algorithm>
+#include <cstdlib>
+#include <list>
+#include <mutex>
+
+#include "zp_internal.hpp"
+
+namespace zp {
+
+zp_status validate_modes(const int32_t *n, const int32_t *m, int64_t M, int64_t *bad)
+{
+    for (int64_t i = 0; i < M; ++i) {
+        const int64_t a = m[i] < 0 ? -(int64_t)m[i] : (int64_t)m[i];
+        // Sec. 2: n >= 0, |m| <= n, n - |m| even.
+        if (n[i] < 0 || a > n[i] || ((n[i] - a) & 1) || n[i] > ZP_N_MAX) {
+            *bad = i;
+            return ZP_ERR_MODE;
+        }
+    }
+    return ZP_OK;
+}
+
+// Ratio of two exactly representable integers: correctly rounded.
+static double ratio(int64_t num, int64_t den) { return (double)num / (double)den; }
+
+// (-1)^K C(K + alpha, K), rounded to double from 64-bit-significand
+// arithmetic (at most ~2K roundings of 2^-64 each before the final one).
+static double signed_binom(int K, int alpha)
+{
+    long double v = 1.0L;
+    for (int i = 1; i <= K; ++i) v = v * (long double)(alpha + i) / (long double)i;
+    return (double)((K & 1) ? -v : v);
+}
+
+std::shared_ptr<Plan> build_plan_host(const int32_t *n, const int32_t *m, int64_t M)
+{
+    auto plan = std::make_shared<Plan>();
+    plan->n.assign(n, n + M);
+    plan->m.assign(m, m + M);
+    int amax = -1;
+    for (int64_t i = 0; i < M; ++i) {
+        amax = std::max(amax, std::abs(m[i]));
+        plan->nmax = std::max(plan->nmax, n[i]);
+    }
+    // Emits grouped by alpha; within a chain sorted by K (stable, so
+    // duplicates keep the caller's column order).
+    std::vector<std::vector<Emit>> by_alpha(amax + 1);
+    for (int64_t i = 0; i < M; ++i) {
+        const int a = std::abs(m[i]);
+        Emit e{};
+        e.K = (n[i] - a) / 2;
+        e.col = (int32_t)i;
+        e.flags = m[i] < 0 ? 1 : 0;
+        e.a_lo = signed_binom(e.K, a);
+        by_alpha[a].push_back(e);
+    }
+    struct Tmp {
+        Chain c;
+        double cost;
+    };
+    std::vector<Tmp> tmp;
+    for (int a = 0; a <= amax; ++a) {
+        auto &v = by_alpha[a];
+        if (v.empty()) continue;
+        std::stable_sort(v.begin(), v.end(), [](const Emit &x, const Emit &y) { return x.K < y.K; });
+        Chain c{};
+        c.alpha = a;
+        c.kmax = v.back().K;
+        c.coef_off = (int32_t)plan->coefs.size();
+        c.emit_off = (int32_t)plan->emits.size();
+        c.emit_cnt = (int32_t)v.size();
+        for (int k = 1; k <= c.kmax; ++k) {
+            const int64_t K = k, A = a;
+            Coef cf{};
+            if (k == 1) {
+                cf.cc_lo = 0.0;
+                cf.cc_hi = 0.0;
+            } else {
+                cf.cc_lo = ratio((K - 1) * (K - 1) * (2 * K + A), (K + A) * (K + A) * (2 * K + A - 2));
+                cf.cc_hi = ratio((K + A - 1) * (K - 1) * (2 * K + A), K * (K + A) * (2 * K + A - 2));
+            }
+            cf.bs_lo = ratio((2 * K + A - 1) * (2 * K + A), 2 * (K + A) * (K + A));
+            cf.bs_hi = ratio((2 * K + A - 1) * (2 * K + A), 2 * K * (K + A));
+            plan->coefs.push_back(cf);
+        }
+        plan->emits.insert(plan->emits.end(), v.begin(), v.end());
+        // Work estimate: stores dominate; the recurrence costs about one
+        // store-equivalent per few steps.
+        tmp.push_back({c, 4.0 * c.emit_cnt + 0.5 * c.kmax});
+    }
+    std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp &x, const Tmp &y) { return x.cost > y.cost; });
+    for (auto &t : tmp) plan->chains.push_back(t.c);
+    return plan;
+}
+
+Plan::~Plan()
+{
+    if (dmem) {
+        int cur = -1;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(device);
+        (void)hipDeviceSynchronize(); // kernels may still read the tables
+        (void)hipFree(dmem);
+        if (cur >= 0) (void)hipSetDevice(cur);
+    }
+}
+
+static zp_status upload(Plan &p)
+{
+    const size_t a = p.chains.size() * sizeof(Chain);
+    const size_t b = std::max<size_t>(p.coefs.size(), 1) * sizeof(Coef);
+    const size_t c = p.emits.size() * sizeof(Emit);
+    const size_t off_b = (a + 255) / 256 * 256;
+    const size_t off_c = off_b + (b + 255) / 256 * 256;
+    const size_t total = off_c + c;
+    std::vector<unsigned char> host(total, 0);
+    std::copy_n((const unsigned char *)p.chains.data(), a, host.data());
+    if (!p.coefs.empty()) std::copy_n((const unsigned char *)p.coefs.data(), p.coefs.size() * sizeof(Coef), host.data() + off_b);
+    std::copy_n((const unsigned char *)p.emits.data(), c, host.data() + off_c);
+    zp_status st = hip_check(hipMalloc(&p.dmem, total), "hipMalloc(plan)");
+    if (st != ZP_OK) return st;
+    st = hip_check(hipMemcpy(p.dmem, host.data(), total, hipMemcpyHostToDevice), "hipMemcpy(plan)");
+    if (st != ZP_OK) return st;
+    p.d_chains = (const Chain *)p.dmem;
+    p.d_coefs = (const Coef *)((unsigned char *)p.dmem + off_b);
+    p.d_emits = (const Emit *)((unsigned char *)p.dmem + off_c);
+    return ZP_OK;
+}
+
+namespace {
+std::mutex g_mu;
+// Most recently used first.  Heap-allocated and never destroyed, so no HIP
+// call runs during static destruction at process exit.
+std::list<std::shared_ptr<Plan>> &g_cache = *new std::list<std::shared_ptr<Plan>>();
+
+size_t cache_capacity()
+{
+    static size_t cap = [] {
+        const char *e = std::getenv("ZP_PLAN_CACHE");
+        long v = e ? std::strtol(e, nullptr, 10) : 16;
+        return (size_t)std::max(1L, v);
+    }();
+    return cap;
+}
+} // namespace
+
+zp_status get_plan(const int32_t *n, const int32_t *m, int64_t M, std::shared_ptr<Plan> *out)
+{
+    int dev = 0;
+    zp_status st = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (st != ZP_OK) return st;
+    std::lock_guard<std::mutex> lock(g_mu);
+    for (auto it = g_cache.begin(); it != g_cache.end(); ++it) {
+        Plan &p = **it;
+        if (p.device == dev && (int64_t)p.n.size() == M && std::equal(p.n.begin(), p.n.end(), n) &&
+            std::equal(p.m.begin(), p.m.end(), m)) {
+            g_cache.splice(g_cache.begin(), g_cache, it);
+            *out = g_cache.front();
+            return ZP_OK;
+        }
+    }
+    auto plan = build_plan_host(n, m, M);
+    plan->device = dev;
+    st = upload(*plan);
+    if (st != ZP_OK) return st;
+    g_cache.push_front(plan);
+    while (g_cache.size() > cache_capacity()) g_cache.pop_back();
+    *out = plan;
+    return ZP_OK;
+}
+
+void clear_plans()
+{
+    std::list<std::shared_ptr<Plan>> drop;
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        drop.swap(g_cache);
+    }
+    drop.clear();
+}
+
+} // namespace zp

@@ -1,0 +1,347 @@
+// Zernike series f = Z^T c and its adjoint: host orchestration of the basis
+// kernel, the conversion kernels and the MFMA contractions.
+//
+// Forward, per chunk of points [p0, p0+Pc):
+//   1. basis Z of the chunk in the contraction type (zero padded) -> cache or ws
+//      (with a cache, also dZ/dr and dZ/dtheta for the backward)
+//   2. f[p0.., :] = Z^T c                     (GEMM, K = modes)
+// Backward, per chunk:
+//   1. Z, dZ/dr, dZ/dtheta from the cache, or recomputed into ws
+//   2. g of the chunk converted to the contraction type
+//   3. grad_c (+)= Z g                         (split-K GEMM, K = points, then a
+//                                               fixed-order reduction; chunks add
+//                                               in order)
+//   4. H = g c^T tile by tile (K = coefficient sets) with the epilogue
+//      grad_r[p] = sum_k H[p][k] dZ_k/dr(p), grad_theta likewise; H is never
+//      stored.  Per-tile partial sums are reduced in a fixed order.
+#include <algorithm>
+#include <cstring>
+
+#include "series.hpp"
+
+namespace zp {
+zp_status check_modes_arg(const int32_t *n, const int32_t *m, int64_t M);
+}
+
+using namespace zp;
+
+namespace {
+
+int ct_of(int32_t prec) { return prec == ZP_FP64 ? CT_F64 : prec == ZP_FP32 ? CT_F32 : CT_BF3; }
+size_t dsize_of(int ct) { return ct == CT_F64 ? 8 : 4; } // dZ/dr, dZ/dtheta planes
+size_t al(size_t x) { return (x + 255) / 256 * 256; }
+
+// Cache: Z in the contraction type [Mp][Pp], then dZ/dr and dZ/dtheta [M][Pp].
+struct CacheLayout {
+    int64_t Mp, Pp;
+    size_t z_off, zr_off, zt_off, total;
+    CacheLayout(int64_t M, int64_t P, int ct)
+    {
+        Mp = pad_up(M);
+        Pp = pad_up(P);
+        z_off = 0;
+        zr_off = al(ct_bytes(ct) * (size_t)Mp * (size_t)Pp);
+        zt_off = zr_off + al(dsize_of(ct) * (size_t)M * (size_t)Pp);
+        total = zt_off + al(dsize_of(ct) * (size_t)M * (size_t)Pp);
+    }
+};
+
+// Split-K count for grad_c: enough workgroups to fill the chip.
+int splits_for(int64_t M, int64_t B, int64_t Kp, int ct)
+{
+    const int64_t tiles = ((M + 63) / 64) * ((B + 63) / 64);
+    int64_t s = std::max<int64_t>(1, (1024 + tiles - 1) / tiles);
+    s = std::min<int64_t>(s, Kp / kPad);
+    while (s > 1 && (Kp % (s * kPad)) != 0) --s; // each split a whole number of pads
+    (void)ct;
+    return (int)s;
+}
+
+// Workspace for one chunk of Pc points.
+struct WsLayout {
+    int64_t Mp, Bp, Pcp;
+    int S, T;
+    size_t c_off, ct_off, z_off, zr_off, zt_off, g_off, gt_off, pc_off, pr_off, total;
+    WsLayout(int64_t M, int64_t Pc, int64_t B, int ct, bool fwd, bool bwd, bool have_cache)
+    {
+        Mp = pad_up(M);
+        Bp = pad_up(B);
+        Pcp = pad_up(Pc);
+        const size_t e = ct_bytes(ct);
+        S = splits_for(M, B, Pcp, ct);
+        T = (int)((M + rowdot_bn(ct) - 1) / rowdot_bn(ct));
+        size_t o = 0;
+        c_off = o; // c [Mp][Bp]
+        o += al(e * (size_t)Mp * (size_t)Bp);
+        ct_off = o; // c^T [Bp][Mp] (bf16 forward)
+        if (ct == CT_BF3 && fwd) o += al(e * (size_t)Bp * (size_t)Mp);
+        z_off = zr_off = zt_off = o;
+        if (!have_cache) {
+            o += al(e * (size_t)Mp * (size_t)Pcp);
+            zr_off = o;
+            if (bwd) o += al(dsize_of(ct) * (size_t)M * (size_t)Pcp);
+            zt_off = o;
+            if (bwd) o += al(dsize_of(ct) * (size_t)M * (size_t)Pcp);
+        }
+        g_off = gt_off = pc_off = pr_off = o;
+        if (bwd) {
+            o += al(e * (size_t)Pcp * (size_t)Bp); // g [Pcp][Bp]
+            gt_off = o;
+            if (ct == CT_BF3) o += al(e * (size_t)Bp * (size_t)Pcp); // g^T [Bp][Pcp]
+            pc_off = o;
+            o += al(8 * (size_t)S * (size_t)M * (size_t)B); // grad_c split-K partials
+            pr_off = o;
+            o += al(8 * (size_t)T * 2 * (size_t)Pc); // row-dot partials
+        }
+        total = o;
+    }
+};
+
+// Largest chunk (multiple of kPad, <= P) whose workspace fits ws_bytes; 0 if none.
+int64_t chunk_for(int64_t M, int64_t P, int64_t B, int ct, bool fwd, bool bwd, bool have_cache, size_t ws_bytes)
+{
+    if (WsLayout(M, P, B, ct, fwd, bwd, have_cache).total <= ws_bytes) return P;
+    int64_t lo = 0, hi = pad_up(P) / kPad; // in units of kPad
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (WsLayout(M, mid * kPad, B, ct, fwd, bwd, have_cache).total <= ws_bytes)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return std::min<int64_t>(lo * kPad, P);
+}
+
+zp_status common_checks(const int32_t *n, const int32_t *m, int64_t M, int64_t P, int64_t B, int32_t prec)
+{
+    zp_status st = check_modes_arg(n, m, M);
+    if (st != ZP_OK) return st;
+    if (P < 0 || B < 0) return set_error(ZP_ERR_ARG, "negative P or B");
+    if (prec < ZP_FP64 || prec > ZP_BF16X3) return set_error(ZP_ERR_PREC, "prec must be ZP_FP64, ZP_FP32 or ZP_BF16X3");
+    return ZP_OK;
+}
+
+// Basis of points [p0, p0+Pc) into the given planes (Z in type ct, derivative planes in dsize).
+zp_status basis_into(const Plan &plan, const double *r, const double *th, int64_t p0, int64_t Pc, int ct,
+                     void *z, void *zr, void *zt, int64_t ld, int64_t Mp, int64_t M, hipStream_t s)
+{
+    Planes o{};
+    o.ld = ld;
+    o.sub = Mp * ld;
+    o.plane[0] = z;
+    o.fmt[0] = ct == CT_F64 ? F64 : ct == CT_F32 ? F32 : B16X3;
+    const int dfmt = ct == CT_F64 ? F64 : F32;
+    o.plane[1] = zr;
+    o.fmt[1] = dfmt;
+    o.plane[4] = zt;
+    o.fmt[4] = dfmt;
+    zp_status st = launch_zero_pad(z, ct, M, Pc, Mp, ld, Mp * ld, s);
+    if (st != ZP_OK) return st;
+    return launch_chain_kernel(plan, r + p0, th + p0, Pc, zr ? 1 : 0, true, o, s);
+}
+
+} // namespace
+
+extern "C" {
+
+zp_status zp_series_cache_bytes(int64_t M, int64_t P, int32_t prec, size_t *bytes)
+{
+    if (!bytes || M < 0 || P < 0) return set_error(ZP_ERR_ARG, "bad argument");
+    if (prec < ZP_FP64 || prec > ZP_BF16X3) return set_error(ZP_ERR_PREC, "unknown prec");
+    *bytes = CacheLayout(M, P, ct_of(prec)).total;
+    return ZP_OK;
+}
+
+zp_status zp_series_workspace(int64_t M, int64_t P, int64_t B, int32_t prec, size_t *full_bytes, size_t *min_bytes)
+{
+    if (!full_bytes || M < 0 || P < 0 || B < 0) return set_error(ZP_ERR_ARG, "bad argument");
+    if (prec < ZP_FP64 || prec > ZP_BF16X3) return set_error(ZP_ERR_PREC, "unknown prec");
+    const int ct = ct_of(prec);
+    // Sized for the most demanding use: backward without a cache.
+    *full_bytes = std::max(WsLayout(M, P, B, ct, true, true, false).total, (size_t)256);
+    if (min_bytes) *min_bytes = std::max(WsLayout(M, std::min<int64_t>(P, kPad), B, ct, true, true, false).total, (size_t)256);
+    return ZP_OK;
+}
+
+zp_status zp_series_fwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r, const double *d_theta,
+                        int64_t P, const double *d_c, int64_t B, int32_t prec, double *d_f, void *d_cache, void *d_ws,
+                        size_t ws_bytes, void *stream)
+{
+    zp_status st = common_checks(h_n, h_m, M, P, B, prec);
+    if (st != ZP_OK) return st;
+    if (M == 0 || P == 0 || B == 0) return ZP_OK;
+    if (!d_r || !d_theta || !d_c || !d_f) return set_error(ZP_ERR_ARG, "null pointer");
+    if (!d_ws || ((uintptr_t)d_ws & 255)) return set_error(ZP_ERR_ARG, "workspace must be non-null and 256-byte aligned");
+    if ((uintptr_t)d_cache & 255) return set_error(ZP_ERR_ARG, "cache must be 256-byte aligned");
+    const int ct = ct_of(prec);
+    const bool have_cache = d_cache != nullptr;
+    const int64_t Pc = chunk_for(M, P, B, ct, true, false, have_cache, ws_bytes);
+    if (Pc <= 0) return set_error(ZP_ERR_WORKSPACE, "workspace smaller than the minimum (zp_series_workspace)");
+    hipStream_t s = (hipStream_t)stream;
+    std::shared_ptr<Plan> plan;
+    st = get_plan(h_n, h_m, M, &plan);
+    if (st != ZP_OK) return st;
+
+    const WsLayout L(M, Pc, B, ct, true, false, have_cache);
+    char *ws = (char *)d_ws;
+    const int64_t Mp = L.Mp, Bp = L.Bp;
+    // c in the layout the forward's B operand wants: k (modes) contiguous for bf16.
+    void *cbuf = ws + (ct == CT_BF3 ? L.ct_off : L.c_off);
+    if (ct == CT_BF3)
+        st = launch_convert(d_c, M, B, B, ct, cbuf, Mp, Bp, Bp * Mp, true, s);
+    else
+        st = launch_convert(d_c, M, B, B, ct, cbuf, Bp, Mp, Mp * Bp, false, s);
+    if (st != ZP_OK) return st;
+
+    const CacheLayout CL(M, P, ct);
+    if (have_cache) {
+        char *cache = (char *)d_cache;
+        st = basis_into(*plan, d_r, d_theta, 0, P, ct, cache + CL.z_off, cache + CL.zr_off, cache + CL.zt_off, CL.Pp,
+                        Mp, M, s);
+        if (st != ZP_OK) return st;
+    }
+    for (int64_t p0 = 0; p0 < P; p0 += Pc) {
+        const int64_t pc = std::min(Pc, P - p0);
+        const void *z;
+        int64_t ldz, zsub;
+        if (have_cache) {
+            z = (const char *)d_cache + CL.z_off + ct_bytes(ct) / (ct == CT_BF3 ? 3 : 1) * (size_t)p0;
+            ldz = CL.Pp;
+            zsub = Mp * CL.Pp;
+        } else {
+            const int64_t pcp = pad_up(pc);
+            st = basis_into(*plan, d_r, d_theta, p0, pc, ct, ws + L.z_off, nullptr, nullptr, pcp, Mp, M, s);
+            if (st != ZP_OK) return st;
+            z = ws + L.z_off;
+            ldz = pcp;
+            zsub = Mp * pcp;
+        }
+        GemmDesc g{};
+        g.ct = ct;
+        g.a = Operand{z, ldz, zsub, false}; // A(i=p, k=q) = Z[q][p]
+        if (ct == CT_BF3)
+            g.b = Operand{cbuf, Mp, Bp * Mp, true}; // B(k=q, j=b) = c^T[b][q]
+        else
+            g.b = Operand{cbuf, Bp, Mp * Bp, false}; // B(k=q, j=b) = c[q][b]
+        g.M = pc;
+        g.N = B;
+        g.K = Mp;
+        g.splits = 1;
+        g.epi = EPI_STORE;
+        g.C = d_f + p0 * B;
+        g.ldc = B;
+        st = launch_gemm(g, s);
+        if (st != ZP_OK) return st;
+    }
+    return ZP_OK;
+}
+
+zp_status zp_series_bwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r, const double *d_theta,
+                        int64_t P, const double *d_c, int64_t B, int32_t prec, const double *d_g, const void *d_cache,
+                        double *d_grad_c, double *d_grad_r, double *d_grad_theta, void *d_ws, size_t ws_bytes,
+                        void *stream)
+{
+    zp_status st = common_checks(h_n, h_m, M, P, B, prec);
+    if (st != ZP_OK) return st;
+    if (M == 0 || P == 0 || B == 0) return ZP_OK;
+    if (!d_r || !d_theta || !d_c || !d_g) return set_error(ZP_ERR_ARG, "null pointer");
+    if (!d_ws || ((uintptr_t)d_ws & 255)) return set_error(ZP_ERR_ARG, "workspace must be non-null and 256-byte aligned");
+    if (!d_grad_c && !d_grad_r && !d_grad_theta) return ZP_OK;
+    if ((uintptr_t)d_cache & 255) return set_error(ZP_ERR_ARG, "cache must be 256-byte aligned");
+    const int ct = ct_of(prec);
+    const bool have_cache = d_cache != nullptr;
+    const int64_t Pc = chunk_for(M, P, B, ct, false, true, have_cache, ws_bytes);
+    if (Pc <= 0) return set_error(ZP_ERR_WORKSPACE, "workspace smaller than the minimum (zp_series_workspace)");
+    hipStream_t s = (hipStream_t)stream;
+    std::shared_ptr<Plan> plan;
+    st = get_plan(h_n, h_m, M, &plan);
+    if (st != ZP_OK) return st;
+
+    const WsLayout L(M, Pc, B, ct, false, true, have_cache);
+    char *ws = (char *)d_ws;
+    const int64_t Mp = L.Mp, Bp = L.Bp;
+    const bool need_rt = d_grad_r || d_grad_theta;
+    // c [Mp][Bp]: H's B operand, element (x = q, k = b), k contiguous.
+    void *cbuf = ws + L.c_off;
+    if (need_rt) {
+        st = launch_convert(d_c, M, B, B, ct, cbuf, Bp, Mp, Mp * Bp, false, s);
+        if (st != ZP_OK) return st;
+    }
+    const CacheLayout CL(M, P, ct);
+    const size_t esz = ct == CT_BF3 ? 2 : ct_bytes(ct);
+    for (int64_t p0 = 0; p0 < P; p0 += Pc) {
+        const int64_t pc = std::min(Pc, P - p0);
+        const int64_t pcp = pad_up(pc);
+        const void *z, *zr, *zt;
+        int64_t ldz, zsub;
+        if (have_cache) {
+            const char *cache = (const char *)d_cache;
+            z = cache + CL.z_off + esz * (size_t)p0;
+            zr = cache + CL.zr_off + dsize_of(ct) * (size_t)p0;
+            zt = cache + CL.zt_off + dsize_of(ct) * (size_t)p0;
+            ldz = CL.Pp;
+            zsub = Mp * CL.Pp;
+        } else {
+            st = basis_into(*plan, d_r, d_theta, p0, pc, ct, ws + L.z_off, ws + L.zr_off, ws + L.zt_off, pcp, Mp, M, s);
+            if (st != ZP_OK) return st;
+            z = ws + L.z_off;
+            zr = ws + L.zr_off;
+            zt = ws + L.zt_off;
+            ldz = pcp;
+            zsub = Mp * pcp;
+        }
+        // g rows of this chunk: [pcp][Bp] (and [Bp][pcp] for bf16's grad_c operand)
+        void *gbuf = ws + L.g_off;
+        st = launch_convert(d_g + p0 * B, pc, B, B, ct, gbuf, Bp, pcp, pcp * Bp, false, s);
+        if (st != ZP_OK) return st;
+        if (ct == CT_BF3 && d_grad_c) {
+            st = launch_convert(d_g + p0 * B, pc, B, B, ct, ws + L.gt_off, pcp, Bp, Bp * pcp, true, s);
+            if (st != ZP_OK) return st;
+        }
+        if (d_grad_c) {
+            GemmDesc g{};
+            g.ct = ct;
+            g.a = Operand{z, ldz, zsub, true}; // A(i=q, k=p) = Z[q][p]
+            if (ct == CT_BF3)
+                g.b = Operand{ws + L.gt_off, pcp, Bp * pcp, true}; // B(k=p, j=b) = g^T[b][p]
+            else
+                g.b = Operand{gbuf, Bp, pcp * Bp, false}; // B(k=p, j=b) = g[p][b]
+            g.M = M;
+            g.N = B;
+            g.K = pcp;
+            g.splits = splits_for(M, B, pcp, ct);
+            g.epi = EPI_PARTIAL;
+            g.C = (double *)(ws + L.pc_off);
+            g.ldc = B;
+            st = launch_gemm(g, s);
+            if (st != ZP_OK) return st;
+            st = launch_splitk_reduce(g.C, g.splits, M, B, d_grad_c, B, p0 > 0, s);
+            if (st != ZP_OK) return st;
+        }
+        if (need_rt) {
+            GemmDesc g{};
+            g.ct = ct;
+            g.a = Operand{gbuf, Bp, pcp * Bp, true};  // A(i=p, k=b) = g[p][b]
+            g.b = Operand{cbuf, Bp, Mp * Bp, true};   // B(k=b, j=q) = c[q][b]
+            g.M = pc;
+            g.N = M;
+            g.K = Bp;
+            g.splits = 1;
+            g.epi = EPI_ROWDOT;
+            g.D1 = zr;
+            g.D2 = zt;
+            g.ldd = ldz;
+            g.d_f32 = ct != CT_F64;
+            g.part = (double *)(ws + L.pr_off);
+            st = launch_gemm(g, s);
+            if (st != ZP_OK) return st;
+            st = launch_rowdot_reduce(g.part, (int)((M + rowdot_bn(ct) - 1) / rowdot_bn(ct)), pc,
+                                      d_grad_r ? d_grad_r + p0 : nullptr, d_grad_theta ? d_grad_theta + p0 : nullptr,
+                                      s);
+            if (st != ZP_OK) return st;
+        }
+    }
+    return ZP_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,73 @@
+// Internal declarations for the Zernike series (contraction of the basis with
+// coefficient sets) and its adjoint.
+#pragma once
+
+#include "zp_internal.hpp"
+
+namespace zp {
+
+// Contraction element types.  BF3 is a value split into three bf16 planes
+// (hi, mid, lo) stored `sub` elements apart.
+enum CType : int { CT_F64 = 0, CT_F32 = 1, CT_BF3 = 2 };
+
+inline size_t ct_bytes(int ct) { return ct == CT_F64 ? 8 : ct == CT_F32 ? 4 : 6; }
+
+// All GEMM operands live in zero-padded buffers whose dimensions are
+// multiples of kPad, so tile loads never need bounds checks.
+constexpr int64_t kPad = 128;
+inline int64_t pad_up(int64_t x) { return (x + kPad - 1) / kPad * kPad; }
+
+// Operand of C(i,j) = sum_k A(i,k) B(k,j).  `kc` true: contiguous along k
+// (element (x,k) at base[x*ld + k]); false: contiguous along the other index
+// (element (x,k) at base[k*ld + x]).  `sub` separates the BF3 planes.
+struct Operand {
+    const void *base;
+    int64_t ld;
+    int64_t sub;
+    bool kc;
+};
+
+enum Epi : int {
+    EPI_STORE = 0,   // C[i*ldc + j] = acc (FP64)
+    EPI_PARTIAL = 1, // split-K: C + split*M*ldc, reduced later
+    EPI_ROWDOT = 2   // part[jtile][0|1][i] = sum_j acc(i,j) D1|D2[j*ldd + i]
+};
+
+struct GemmDesc {
+    int ct;
+    Operand a, b;
+    int64_t M, N, K; // output M x N (unpadded); K a multiple of kPad
+    int splits;      // split-K count (EPI_PARTIAL)
+    int epi;
+    double *C;
+    int64_t ldc;
+    const void *D1, *D2; // EPI_ROWDOT: derivative planes, FP64 or FP32
+    int64_t ldd;
+    bool d_f32;
+    double *part; // EPI_ROWDOT output partials [ceil(N/BN)][2][M]
+};
+
+// Column-tile width of the row-dot epilogue for a compute type (partials
+// buffer has ceil(N / rowdot_bn(ct)) tiles).
+int rowdot_bn(int ct);
+
+zp_status launch_gemm(const GemmDesc &g, hipStream_t s);
+
+// dst (compute type, [R_pad][C_pad] or transposed [C_pad][R_pad]) from a
+// row-major FP64 src [R][C] (leading dimension lds); zero padding.
+zp_status launch_convert(const double *src, int64_t R, int64_t C, int64_t lds, int ct, void *dst, int64_t ldd,
+                         int64_t rows_pad, int64_t sub, bool transpose, hipStream_t s);
+
+// Zero the pad region of a [rows_pad][ld] compute-type plane set whose
+// valid block is [rows][cols].
+zp_status launch_zero_pad(void *dst, int ct, int64_t rows, int64_t cols, int64_t rows_pad, int64_t ld, int64_t sub,
+                          hipStream_t s);
+
+// C[i*ldc + j] (=|+=) sum_s part[s][i][j] for s = 0..S-1, fixed order.
+zp_status launch_splitk_reduce(const double *part, int S, int64_t M, int64_t N, double *C, int64_t ldc,
+                               bool accumulate, hipStream_t s);
+
+// out1[p] = sum_t part[t][0][p], out2[p] = sum_t part[t][1][p] (either nullable).
+zp_status launch_rowdot_reduce(const double *part, int T, int64_t P, double *out1, double *out2, hipStream_t s);
+
+} // namespace zp

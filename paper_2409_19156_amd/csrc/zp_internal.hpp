@@ -1,0 +1,110 @@
+// Internal declarations shared by the host API (zp_api.cpp), the plan builder
+// (plan.cpp) and the HIP kernels.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/zp.h"
+
+namespace zp {
+
+// ---------------------------------------------------------------- plan --
+//
+// A plan is everything about a mode list that does not depend on the points:
+// the modes grouped by alpha = |m| into recurrence chains (one chain per
+// alpha, shared by every n of that alpha, as in Algorithm 1), the per-step
+// recurrence coefficients of each chain, and the list of (K, column) pairs
+// each chain must emit.
+//
+// Recurrence (endpoint-anchored difference form of the beta = 0 Jacobi
+// recurrence of Sec. 2).  With x = 1 - 2r^2 and v_k the Jacobi polynomial
+// P_k^{(alpha,0)}(x) normalised to 1 at one end of [-1, 1]:
+//   low anchor (x = +1):  s = 2r^2,      v_k = P_k / C(k+alpha, k)
+//   high anchor (x = -1): s = 2(1-r^2),  v_k = (-1)^k P_k
+// the three-term recurrence becomes, with d_k = v_k - v_{k-1},
+//   d_k = cc_k d_{k-1} - bs_k s v_{k-1},   v_k = v_{k-1} + d_k,
+//   v_0 = 1, d_0 = 0, cc_1 = 0,
+// low:  cc_k = (k-1)^2 (2k+alpha) / ((k+alpha)^2 (2k+alpha-2)),
+//       bs_k = (2k+alpha-1)(2k+alpha) / (2 (k+alpha)^2)
+// high: cc_k = (k+alpha-1)(k-1)(2k+alpha) / (k (k+alpha)(2k+alpha-2)),
+//       bs_k = (2k+alpha-1)(2k+alpha) / (2k (k+alpha)).
+// It is an exact algebraic rewrite of the paper's recurrence (the sum rule
+// of its coefficients makes v = 1 at s = 0 a fixed point), so the end point
+// is reproduced exactly and rounding errors vanish with s.
+struct Chain {
+    int32_t alpha;    // |m| of every mode on this chain
+    int32_t kmax;     // largest K requested on this chain
+    int32_t coef_off; // first Coef of this chain (entry k-1 holds step k)
+    int32_t emit_off; // first Emit of this chain
+    int32_t emit_cnt; // number of Emits
+    int32_t pad;
+};
+
+struct Coef {
+    double cc_lo, bs_lo, cc_hi, bs_hi;
+};
+
+struct Emit {
+    int32_t K;     // Jacobi degree (n - alpha)/2
+    int32_t col;   // output column (position in the caller's mode list)
+    int32_t flags; // bit 0: m < 0 (sin column of the basis)
+    int32_t pad;
+    double a_lo; // (-1)^K C(K+alpha, K): low-anchor factor from v_K to R / r^alpha
+};
+
+struct Plan {
+    int device = -1;
+    std::vector<int32_t> n, m; // the key
+    std::vector<Chain> chains; // in launch order (most work first)
+    std::vector<Coef> coefs;
+    std::vector<Emit> emits;
+    int32_t nmax = 0;
+    // device copies (one allocation)
+    void *dmem = nullptr;
+    const Chain *d_chains = nullptr;
+    const Coef *d_coefs = nullptr;
+    const Emit *d_emits = nullptr;
+    ~Plan();
+};
+
+// Validates the modes; returns ZP_OK or ZP_ERR_MODE (with the offending index
+// in *bad).
+zp_status validate_modes(const int32_t *n, const int32_t *m, int64_t M, int64_t *bad);
+
+// Host-side construction of a plan (no device work).
+std::shared_ptr<Plan> build_plan_host(const int32_t *n, const int32_t *m, int64_t M);
+
+// Cached plan for the current device, uploaded on first use.
+zp_status get_plan(const int32_t *n, const int32_t *m, int64_t M, std::shared_ptr<Plan> *out);
+void clear_plans();
+
+// ------------------------------------------------------------- outputs --
+
+enum PlaneFmt : int32_t { F64 = 0, F32 = 1, B16X3 = 2 };
+
+// Where the chain kernel writes.  plane[q] for q = 0..4 is R (or Z), d/dr,
+// d2/dr2, d3/dr3, d/dtheta; null planes are not written.  Column i of a plane
+// starts ld elements after column i-1.  A B16X3 plane is three bf16 planes
+// (hi, mid, lo) sub elements apart.
+struct Planes {
+    void *plane[5];
+    int64_t ld;
+    int64_t sub;
+    int32_t fmt[5];
+};
+
+// Launch the chain kernel: radial only (angular = false) or basis.  J is the
+// highest radial derivative needed (0..3).
+zp_status launch_chain_kernel(const Plan &plan, const double *d_r, const double *d_theta, int64_t P,
+                              int J, bool angular, const Planes &out, hipStream_t s);
+
+// Error plumbing.
+zp_status set_error(zp_status s, const std::string &msg);
+zp_status hip_check(hipError_t e, const char *what);
+
+} // namespace zp

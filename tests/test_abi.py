@@ -1,0 +1,122 @@
+"""The C ABI (include/zp.h) on the CPU: the library loads, exports every
+declared symbol, and rejects bad arguments on the host before any HIP call.
+
+No test here launches device work: error paths return before the first HIP
+call, and empty problems (M, P or B zero) are no-ops.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2409_19156_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+OK, ERR_MODE, ERR_ARG, ERR_ORDER, ERR_WS, ERR_HIP, ERR_PREC = range(7)
+FAKE = ctypes.c_void_p(0x10000)  # never dereferenced: every call below fails validation first
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "zp.h")).read()
+    return sorted(set(re.findall(r"\b(zp_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    declared = _declared()
+    assert set(declared) == set(_lib.EXPORTS), declared
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_abi_version_and_status_strings(lib):
+    assert lib.zp_abi_version() == 1
+    for code in range(7):
+        assert lib.zp_status_string(code)
+    assert b"unknown" in lib.zp_status_string(99)
+
+
+def _modes(n, m):
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    m = np.ascontiguousarray(m, dtype=np.int32)
+    return n, m
+
+
+@pytest.mark.parametrize("n,m", [([-1], [0]), ([3], [0]), ([2], [4]), ([5], [-6]), ([1001], [1]), ([4, 7], [0, 2])])
+def test_invalid_modes(lib, n, m):
+    n, m = _modes(n, m)
+    assert lib.zp_radial(n.ctypes.data, m.ctypes.data, n.size, FAKE, 4, 0, FAKE, None) == ERR_MODE
+    assert b"violates" in lib.zp_last_error()
+    assert lib.zp_basis(n.ctypes.data, m.ctypes.data, n.size, FAKE, FAKE, 4, 1, FAKE, None) == ERR_MODE
+    assert lib.zp_series_fwd(n.ctypes.data, m.ctypes.data, n.size, FAKE, FAKE, 4, FAKE, 2, 0, FAKE, None, FAKE,
+                             1 << 20, None) == ERR_MODE
+    assert lib.zp_series_bwd(n.ctypes.data, m.ctypes.data, n.size, FAKE, FAKE, 4, FAKE, 2, 0, FAKE, None, FAKE,
+                             FAKE, FAKE, FAKE, 1 << 20, None) == ERR_MODE
+
+
+def test_order_mask_prec_and_sizes(lib):
+    n, m = _modes([2, 3], [0, -1])
+    nd, md = n.ctypes.data, m.ctypes.data
+    for bad in (-1, 4, 7):
+        assert lib.zp_radial(nd, md, 2, FAKE, 4, bad, FAKE, None) == ERR_ORDER
+    for mask in (0, 32, 33):
+        assert lib.zp_basis(nd, md, 2, FAKE, FAKE, 4, mask, FAKE, None) == ERR_ARG
+    assert lib.zp_radial(nd, md, -1, FAKE, 4, 0, FAKE, None) == ERR_ARG
+    assert lib.zp_radial(nd, md, 2, FAKE, -4, 0, FAKE, None) == ERR_ARG
+    assert lib.zp_radial(nd, md, 2, None, 4, 0, FAKE, None) == ERR_ARG
+    assert lib.zp_radial(nd, md, 2, FAKE, 4, 0, None, None) == ERR_ARG
+    assert lib.zp_radial(None, md, 2, FAKE, 4, 0, FAKE, None) == ERR_ARG
+    assert lib.zp_basis(nd, md, 2, FAKE, None, 4, 1, FAKE, None) == ERR_ARG
+    for prec in (-1, 3):
+        assert lib.zp_series_fwd(nd, md, 2, FAKE, FAKE, 4, FAKE, 2, prec, FAKE, None, FAKE, 1 << 20, None) == ERR_PREC
+    assert lib.zp_series_fwd(nd, md, 2, FAKE, FAKE, -4, FAKE, 2, 0, FAKE, None, FAKE, 1 << 20, None) == ERR_ARG
+    assert lib.zp_series_fwd(nd, md, 2, FAKE, FAKE, 4, FAKE, -2, 0, FAKE, None, FAKE, 1 << 20, None) == ERR_ARG
+    # workspace: null / misaligned / too small (all host-side)
+    assert lib.zp_series_fwd(nd, md, 2, FAKE, FAKE, 4, FAKE, 2, 0, FAKE, None, None, 1 << 20, None) == ERR_ARG
+    assert lib.zp_series_fwd(nd, md, 2, FAKE, FAKE, 4, FAKE, 2, 0, FAKE, None, ctypes.c_void_p(0x10008), 1 << 20,
+                             None) == ERR_ARG
+    assert lib.zp_series_fwd(nd, md, 2, FAKE, FAKE, 4, FAKE, 2, 0, FAKE, None, FAKE, 16, None) == ERR_WS
+    assert lib.zp_series_bwd(nd, md, 2, FAKE, FAKE, 4, FAKE, 2, 0, FAKE, None, FAKE, FAKE, FAKE, FAKE, 16,
+                             None) == ERR_WS
+
+
+def test_empty_problems_are_noops(lib):
+    n, m = _modes([2], [0])
+    e = np.zeros(0, dtype=np.int32)
+    assert lib.zp_radial(e.ctypes.data, e.ctypes.data, 0, FAKE, 4, 3, FAKE, None) == OK
+    assert lib.zp_radial(n.ctypes.data, m.ctypes.data, 1, None, 0, 3, None, None) == OK
+    assert lib.zp_basis(n.ctypes.data, m.ctypes.data, 1, None, None, 0, 31, None, None) == OK
+    assert lib.zp_series_fwd(n.ctypes.data, m.ctypes.data, 1, FAKE, FAKE, 4, FAKE, 0, 0, FAKE, None, FAKE, 0,
+                             None) == OK
+
+
+def test_size_queries(lib):
+    full, mn, cb = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    for prec in (0, 1, 2):
+        assert lib.zp_series_workspace(2145, 65536, 1024, prec, ctypes.byref(full), ctypes.byref(mn)) == OK
+        assert 0 < mn.value <= full.value
+        assert full.value % 256 == 0 and mn.value % 256 == 0
+        assert lib.zp_series_cache_bytes(2145, 65536, prec, ctypes.byref(cb)) == OK
+        # at least Z in the contraction type plus two derivative planes
+        per = {0: 8 + 16, 1: 4 + 8, 2: 6 + 8}[prec]
+        assert cb.value >= 2145 * 65536 * per
+    assert lib.zp_series_workspace(-1, 4, 4, 0, ctypes.byref(full), None) == ERR_ARG
+    assert lib.zp_series_workspace(4, 4, 4, 9, ctypes.byref(full), None) == ERR_PREC
+    assert lib.zp_series_cache_bytes(4, 4, 0, None) == ERR_ARG
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    """The Python binding has no fallback: a missing libzp.so is an error."""
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        _lib.load()
