@@ -110,20 +110,18 @@ __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__
     const double s2 = high ? -4.0 : 4.0;         // d2s/dr2
 
     // w[i] = d^i/dr^i r^alpha = alpha!/(alpha-i)! r^(alpha-i), 0 for i > alpha.
+    // Each w[i] is formed the same way whatever J is, so every output
+    // selection gives bitwise identical values.
     double w[J + 1];
-    {
-        const int top = alpha < J ? alpha : J;
-        double pw = ipow(x, alpha - top);
-        for (int i = J; i >= 0; --i) {
-            if (i > top) {
-                w[i] = 0.0;
-                continue;
-            }
-            double f = 1.0;
-            for (int t = 0; t < i; ++t) f *= (double)(alpha - t);
-            w[i] = f * pw;
-            pw *= x;
+#pragma unroll
+    for (int i = 0; i <= J; ++i) {
+        if (i > alpha) {
+            w[i] = 0.0;
+            continue;
         }
+        double f = 1.0;
+        for (int t = 0; t < i; ++t) f *= (double)(alpha - t);
+        w[i] = f * ipow(x, alpha - i);
     }
 
     double cs = 0.0, sn = 0.0;

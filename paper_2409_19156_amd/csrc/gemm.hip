@@ -24,8 +24,9 @@
 // at most kFlush terms.
 //
 // MFMA lane layouts (16x16 blocks): lane l supplies A[l%16][k] and B[k][l%16]
-// for k = l/16 (x4 shapes) or k = 8(l/16)..8(l/16)+7 (bf16 x32 shape); it
-// receives D[4(l/16)+t][l%16], t = 0..3.
+// for k = l/16 (x4 shapes) or k = 8(l/16)..8(l/16)+7 (bf16 x32 shape).  It
+// receives D[4(l/16)+t][l%16], t = 0..3, for the FP32-accumulating shapes and
+// D[l/16+4t][l%16] for the FP64 shape.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -250,6 +251,9 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc g)
     }
     flush();
 
+    // Output row (within the 16-row block) of accumulator element t.
+    auto row_of = [&](int t) -> int { return CT == CT_F64 ? lk + 4 * t : 4 * lk + t; };
+
     auto value = [&](int a, int b, int t) -> double {
         if constexpr (MIXED)
             return acc64[a][b][t];
@@ -266,7 +270,7 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc g)
                 const int64_t j = j0 + wn0 + b * 16 + lx;
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    const int64_t i = i0 + wm0 + a * 16 + 4 * lk + t;
+                    const int64_t i = i0 + wm0 + a * 16 + row_of(t);
                     if (i < g.M && j < g.N) C[i * g.ldc + j] = value(a, b, t);
                 }
             }
@@ -278,7 +282,7 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc g)
         for (int a = 0; a < FM; ++a)
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const int il = wm0 + a * 16 + 4 * lk + t;
+                const int il = wm0 + a * 16 + row_of(t);
                 const int64_t i = i0 + il;
                 double s1 = 0.0, s2 = 0.0;
 #pragma unroll
