@@ -22,6 +22,31 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
+# Measured HBM traffic of the basis kernel on this workload: two rocprofv3
+# --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, median of 5) of
+#   bench.py --steps 3 --warmup 1 --no-series --no-cpu-baseline
+# scaled by what the same counters read for a plain 1 GiB device copy
+#   bench.py --copy-calibration-mb 1024
+# (FETCH_SIZE 524299.5 KiB for 1048576 KiB read: x2.0; WRITE_SIZE 1048576 KiB
+# for 1048576 KiB written: x1.0).  Valid only for the kernel sources it was
+# taken on; reported as null once they change.
+TRAFFIC = {"sources": ("paper_2409_19156_amd/csrc/chain_kernel.hip", "paper_2409_19156_amd/csrc/zp_internal.hpp"),
+           "sha256": "87e103e27b74667e9dfefdaf85578f714dfe82feebb78412dd18cb1f9a96ae86",
+           "fetch_kib": 462.0, "fetch_scale": 1048576.0 / 524299.5,
+           "write_kib": 424780.0, "write_scale": 1.0}
+
+
+def measured_traffic():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != TRAFFIC["sha256"]:
+        return None
+    return (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * TRAFFIC["write_scale"]) * 1024.0
+
 
 def _parse():
     ap = argparse.ArgumentParser()
@@ -30,6 +55,9 @@ def _parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-series", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB, 5 times (for scaling "
+                         "hardware byte counters), then exit")
     ap.add_argument("--cpu-sample-points", type=int, default=0,
                     help="points of the workload the oracle is timed on (0: all)")
     return ap.parse_args()
@@ -114,6 +142,16 @@ def main():
         sys.exit(2)
     import torch
 
+    if args.copy_calibration_mb:
+        n = args.copy_calibration_mb << 20
+        src = torch.ones(n // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n, "copy_calibration_bytes_written": n, "calls": 5}))
+        return
+
     import paper_2409_19156_amd as zp
     import zp_workloads as W
 
@@ -147,6 +185,16 @@ def main():
     value = entries / (ms * 1e-3)
     achieved = bytes_per_launch / (ms * 1e-3) / 1e9
 
+    # Reference streaming-write rate on the same buffer: torch's fill kernel.
+    for _ in range(3):
+        out.zero_()
+    ev0.record(stream)
+    for _ in range(20):
+        out.zero_()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    fill_gbs = out.numel() * 8 / (ev0.elapsed_time(ev1) / 20 * 1e-3) / 1e9
+
     res = {
         "metric": "Zernike basis entries/s FP64 (L=M=50) & series fwd+bwd speedup at stated err",
         "value": value,
@@ -164,9 +212,10 @@ def main():
                                "outputs Z, dZ/dr, d2Z/dr2, d3Z/dr3, dZ/dtheta",
                    "modes": wl.M, "points": wl.P, "outputs": 5, "entries": entries},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "chain_kernel<3,true>", "bytes_per_launch": bytes_per_launch,
-                     "avg_launch_us": ms * 1e3},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "kernel": "chain_kernel<3,true,false>", "bytes_per_launch": bytes_per_launch,
+                     "avg_launch_us": ms * 1e3, "measured_fill_GBs": fill_gbs,
+                     "frac_of_measured_fill": achieved / fill_gbs},
         "first_call_ms": first_call_ms,
         "timed_wall_ms": wall_ms,
     }

@@ -1,7 +1,8 @@
 // Radial Zernike polynomials, their r-derivatives and the full Zernike basis
 // on gfx950 (MI355X).
 //
-// Work decomposition: one lane per point, one workgroup per (256-point tile,
+// Work decomposition: one lane per point (two adjacent points per lane when
+// every output plane is FP64), one workgroup (256 lanes) per (point tile,
 // recurrence chain).  A chain is one alpha = |m| (Algorithm 1 of the paper:
 // the chain P_k^{(alpha,0)}, k = 0..Kmax, serves every requested n of that
 // alpha).  Every lane of a workgroup walks the same chain in lock step, so
@@ -9,9 +10,9 @@
 // as broadcasts.  Each requested (n, m) on the chain is emitted when the walk
 // reaches its degree K = (n - alpha)/2: the lane assembles R and its
 // r-derivatives, applies the angular factor, and stores.  For a fixed column
-// the 64 lanes of a wave store 64 consecutive points: 512 contiguous bytes
-// per FP64 store instruction, marked non-temporal because outputs are not
-// re-read by this kernel.
+// the 64 lanes of a wave store 128 consecutive points: 1 KB contiguous per
+// store instruction (16 bytes per lane), marked non-temporal because outputs
+// are not re-read by this kernel.
 //
 // Arithmetic: the endpoint-anchored difference form of the beta = 0 Jacobi
 // recurrence (see zp_internal.hpp) with the derivatives with respect to
@@ -50,6 +51,18 @@ __device__ __forceinline__ double bf16_to_double(uint16_t h)
     return (double)__uint_as_float((uint32_t)h << 16);
 }
 
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+
+// v ~ hi + mid + lo as three bf16 values; the residuals are exact in FP64.
+__device__ __forceinline__ void split3(double v, uint16_t &h, uint16_t &m, uint16_t &l)
+{
+    h = bf16_rne((float)v);
+    const double r1 = v - bf16_to_double(h);
+    m = bf16_rne((float)r1);
+    const double r2 = r1 - bf16_to_double(m);
+    l = bf16_rne((float)r2);
+}
+
 __device__ __forceinline__ void store_plane(const Planes &o, int q, int64_t idx, double v)
 {
     switch (o.fmt[q]) {
@@ -59,13 +72,10 @@ __device__ __forceinline__ void store_plane(const Planes &o, int q, int64_t idx,
     case F32:
         __builtin_nontemporal_store((float)v, (float *)o.plane[q] + idx);
         break;
-    default: { // B16X3: v ~ hi + mid + lo, residuals exact in FP64
+    default: { // B16X3
         uint16_t *b = (uint16_t *)o.plane[q] + idx;
-        const uint16_t h = bf16_rne((float)v);
-        const double r1 = v - bf16_to_double(h);
-        const uint16_t md = bf16_rne((float)r1);
-        const double r2 = r1 - bf16_to_double(md);
-        const uint16_t l = bf16_rne((float)r2);
+        uint16_t h, md, l;
+        split3(v, h, md, l);
         __builtin_nontemporal_store(h, b);
         __builtin_nontemporal_store(md, b + o.sub);
         __builtin_nontemporal_store(l, b + 2 * o.sub);
@@ -86,7 +96,11 @@ __device__ __forceinline__ double ipow(double x, int e)
     return acc;
 }
 
-template <int J, bool ANG>
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+// NPL points per lane (1, or 2 for FP64-only outputs: each store then writes
+// 16 bytes per lane, 1 KB per wave).
+template <int J, bool ANG, bool KB, int NPL>
 __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__ chains,
                                                        const Coef *__restrict__ coefs,
                                                        const Emit *__restrict__ emits,
@@ -94,91 +108,150 @@ __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__
                                                        const double *__restrict__ theta, int64_t P,
                                                        Planes out)
 {
+    static_assert(NPL == 1 || (NPL == 2 && !KB), "two points per lane only for plain FP64 planes");
     __shared__ Coef tab[kTabChunk];
 
     const Chain ch = chains[blockIdx.y];
     const int alpha = ch.alpha;
-    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool live = p < P;
-    const double x = live ? r[p] : 0.0;
+    const int64_t p0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * NPL;
 
-    // Anchor and s(r).
-    const double x2 = x * x;
-    const bool high = !(x2 < 0.5);
-    const double s = high ? __builtin_fma(-2.0 * x, x, 2.0) : 2.0 * x2;
-    const double s1 = high ? -4.0 * x : 4.0 * x; // ds/dr
-    const double s2 = high ? -4.0 : 4.0;         // d2s/dr2
-
-    // w[i] = d^i/dr^i r^alpha = alpha!/(alpha-i)! r^(alpha-i), 0 for i > alpha.
-    // Each w[i] is formed the same way whatever J is, so every output
-    // selection gives bitwise identical values.
-    double w[J + 1];
+    bool live[NPL], high[NPL];
+    double x[NPL], s[NPL], s1[NPL], s2[NPL], cs[NPL], sn[NPL];
+    double w[NPL][J + 1], v[NPL][J + 1], d[NPL][J + 1];
 #pragma unroll
-    for (int i = 0; i <= J; ++i) {
-        if (i > alpha) {
-            w[i] = 0.0;
-            continue;
+    for (int u = 0; u < NPL; ++u) {
+        live[u] = p0 + u < P;
+        x[u] = live[u] ? r[p0 + u] : 0.0;
+        // Anchor and s(r), ds/dr, d2s/dr2.
+        const double x2 = x[u] * x[u];
+        high[u] = !(x2 < 0.5);
+        s[u] = high[u] ? __builtin_fma(-2.0 * x[u], x[u], 2.0) : 2.0 * x2;
+        s1[u] = high[u] ? -4.0 * x[u] : 4.0 * x[u];
+        s2[u] = high[u] ? -4.0 : 4.0;
+        // w[i] = d^i/dr^i r^alpha = alpha!/(alpha-i)! r^(alpha-i), 0 for
+        // i > alpha.  Each w[i] is formed the same way whatever J is, so
+        // every output selection gives bitwise identical values.
+#pragma unroll
+        for (int i = 0; i <= J; ++i) {
+            if (i > alpha) {
+                w[u][i] = 0.0;
+                continue;
+            }
+            double f = 1.0;
+            for (int t = 0; t < i; ++t) f *= (double)(alpha - t);
+            w[u][i] = f * ipow(x[u], alpha - i);
         }
-        double f = 1.0;
-        for (int t = 0; t < i; ++t) f *= (double)(alpha - t);
-        w[i] = f * ipow(x, alpha - i);
-    }
-
-    double cs = 0.0, sn = 0.0;
-    if (ANG) {
-        const double th = live ? theta[p] : 0.0;
-        // alpha * theta split exactly into ph + pe; then one first-order
-        // correction of sincos(ph) for the tail pe.
-        const double fa = (double)alpha;
-        const double ph = fa * th;
-        const double pe = __builtin_fma(fa, th, -ph);
-        double s0, c0;
-        sincos(ph, &s0, &c0);
-        sn = __builtin_fma(pe, c0, s0);
-        cs = __builtin_fma(-pe, s0, c0);
-    }
-
-    double v[J + 1], d[J + 1];
+        cs[u] = 0.0;
+        sn[u] = 0.0;
+        if (ANG) {
+            const double th = live[u] ? theta[p0 + u] : 0.0;
+            // alpha * theta split exactly into ph + pe; then one first-order
+            // correction of sincos(ph) for the tail pe.
+            const double fa = (double)alpha;
+            const double ph = fa * th;
+            const double pe = __builtin_fma(fa, th, -ph);
+            double s0, c0;
+            sincos(ph, &s0, &c0);
+            sn[u] = __builtin_fma(pe, c0, s0);
+            cs[u] = __builtin_fma(-pe, s0, c0);
+        }
 #pragma unroll
-    for (int i = 0; i <= J; ++i) {
-        v[i] = i == 0 ? 1.0 : 0.0;
-        d[i] = 0.0;
+        for (int i = 0; i <= J; ++i) {
+            v[u][i] = i == 0 ? 1.0 : 0.0;
+            d[u][i] = 0.0;
+        }
     }
 
     const int e_end = ch.emit_off + ch.emit_cnt;
     int e = ch.emit_off;
     int nextK = e < e_end ? emits[e].K : INT_MAX;
 
+    // Staging for the k-blocked bf16 copy of Z: a 128-bit shift register per
+    // plane collects the eight emissions of a group that lies wholly on this
+    // chain piece; groups that straddle a boundary are stored element-wise.
+    uint32_t kbw[KB ? 3 : 1][4] = {};
+
     auto emit_all = [&](int k) {
         while (nextK == k) {
+            const int eidx = e;
             const Emit em = emits[e];
             ++e;
             nextK = e < e_end ? emits[e].K : INT_MAX;
-            // g^(j) = d^j/dr^j v(s(r))
-            double g[J + 1];
-            g[0] = v[0];
-            if (J >= 1) g[1] = s1 * v[1];
-            if (J >= 2) g[2] = __builtin_fma(s1 * s1, v[2], s2 * v[1]);
-            if (J >= 3) g[3] = __builtin_fma(s1 * s1 * s1, v[3], 3.0 * s1 * s2 * v[2]);
-            const double A = high ? 1.0 : em.a_lo;
-            double R[J + 1];
-            R[0] = A * (w[0] * g[0]);
-            if (J >= 1) R[1] = A * __builtin_fma(w[0], g[1], w[1] * g[0]);
-            if (J >= 2) R[2] = A * (__builtin_fma(w[0], g[2], 2.0 * w[1] * g[1]) + w[2] * g[0]);
-            if (J >= 3)
-                R[3] = A * (__builtin_fma(w[0], g[3], 3.0 * w[1] * g[2]) + __builtin_fma(3.0 * w[2], g[1], w[3] * g[0]));
-            if (!live) continue;
-            const int64_t idx = (int64_t)em.col * out.ld + p;
             const bool is_sin = em.flags & 1;
-            const double fac = ANG ? (is_sin ? sn : cs) : 1.0;
+            double val[5][NPL];
 #pragma unroll
-            for (int q = 0; q <= J; ++q)
-                if (out.plane[q]) store_plane(out, q, idx, ANG ? R[q] * fac : R[q]);
-            if (ANG && out.plane[4]) {
+            for (int u = 0; u < NPL; ++u) {
+                // g^(j) = d^j/dr^j v(s(r))
+                double g[J + 1];
+                g[0] = v[u][0];
+                if (J >= 1) g[1] = s1[u] * v[u][1];
+                if (J >= 2) g[2] = __builtin_fma(s1[u] * s1[u], v[u][2], s2[u] * v[u][1]);
+                if (J >= 3) g[3] = __builtin_fma(s1[u] * s1[u] * s1[u], v[u][3], 3.0 * s1[u] * s2[u] * v[u][2]);
+                const double A = high[u] ? 1.0 : em.a_lo;
+                const double *wu = w[u];
+                double R[J + 1];
+                R[0] = A * (wu[0] * g[0]);
+                if (J >= 1) R[1] = A * __builtin_fma(wu[0], g[1], wu[1] * g[0]);
+                if (J >= 2) R[2] = A * (__builtin_fma(wu[0], g[2], 2.0 * wu[1] * g[1]) + wu[2] * g[0]);
+                if (J >= 3)
+                    R[3] = A * (__builtin_fma(wu[0], g[3], 3.0 * wu[1] * g[2]) +
+                                __builtin_fma(3.0 * wu[2], g[1], wu[3] * g[0]));
+                const double fac = ANG ? (is_sin ? sn[u] : cs[u]) : 1.0;
+#pragma unroll
+                for (int q = 0; q <= J; ++q) val[q][u] = ANG ? R[q] * fac : R[q];
                 // d/dtheta of R cos(m theta) = -m R sin(m theta) (m >= 0);
                 // of R sin(|m| theta) = |m| R cos(|m| theta) (m < 0).
                 const double fa = (double)alpha;
-                store_plane(out, 4, idx, is_sin ? fa * R[0] * cs : -fa * R[0] * sn);
+                val[4][u] = ANG ? (is_sin ? fa * R[0] * cs[u] : -fa * R[0] * sn[u]) : 0.0;
+            }
+            const int64_t idx = (int64_t)em.col * out.ld + p0;
+            if (NPL == 2) {
+                // planes are FP64 here; a pair of points is 16 bytes, aligned
+                // because ld and p0 are even
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    if ((q > J && q < 4) || (q == 4 && !ANG) || !out.plane[q]) continue;
+                    double *dst = (double *)out.plane[q] + idx;
+                    if (live[NPL - 1]) {
+                        const d2 pair = {val[q][0], val[q][NPL - 1]};
+                        __builtin_nontemporal_store(pair, (d2 *)dst);
+                    } else if (live[0]) {
+                        __builtin_nontemporal_store(val[q][0], dst);
+                    }
+                }
+                continue;
+            }
+            if (!live[0]) continue;
+#pragma unroll
+            for (int q = 0; q <= J; ++q)
+                if (out.plane[q]) store_plane(out, q, idx, val[q][0]);
+            if (ANG && out.plane[4]) store_plane(out, 4, idx, val[4][0]);
+            if (KB) {
+                uint16_t hv[3];
+                split3(val[0][0], hv[0], hv[1], hv[2]);
+                const int g8 = eidx & ~7;
+                uint16_t *kb = (uint16_t *)out.kb + ((int64_t)(eidx >> 3) * out.kb_ld + p0) * 8;
+                if (g8 >= ch.emit_off && g8 + 8 <= e_end) {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        uint32_t *w4 = kbw[KB ? q : 0];
+                        w4[0] = __builtin_amdgcn_alignbit(w4[1], w4[0], 16);
+                        w4[1] = __builtin_amdgcn_alignbit(w4[2], w4[1], 16);
+                        w4[2] = __builtin_amdgcn_alignbit(w4[3], w4[2], 16);
+                        w4[3] = (w4[3] >> 16) | ((uint32_t)hv[q] << 16);
+                    }
+                    if ((eidx & 7) == 7) {
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) {
+                            const uint32_t *w4 = kbw[KB ? q : 0];
+                            const u4 vv = {w4[0], w4[1], w4[2], w4[3]};
+                            __builtin_nontemporal_store(vv, (u4 *)(kb + q * out.kb_sub));
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) __builtin_nontemporal_store(hv[q], kb + q * out.kb_sub + (eidx & 7));
+                }
             }
         }
     };
@@ -191,29 +264,50 @@ __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__
         __syncthreads();
         for (int kk = 0; kk < cnt; ++kk) {
             const Coef cf = tab[kk];
-            const double cc = high ? cf.cc_hi : cf.cc_lo;
-            const double bs = high ? cf.bs_hi : cf.bs_lo;
-            // All d use the step k-1 values of v; then v advances.
 #pragma unroll
-            for (int i = J; i >= 1; --i) {
-                const double t = __builtin_fma(s, v[i], (double)i * v[i - 1]);
-                d[i] = __builtin_fma(cc, d[i], -bs * t);
+            for (int u = 0; u < NPL; ++u) {
+                const double cc = high[u] ? cf.cc_hi : cf.cc_lo;
+                const double bs = high[u] ? cf.bs_hi : cf.bs_lo;
+                // All d use the step k-1 values of v; then v advances.
+#pragma unroll
+                for (int i = J; i >= 1; --i) {
+                    const double t = __builtin_fma(s[u], v[u][i], (double)i * v[u][i - 1]);
+                    d[u][i] = __builtin_fma(cc, d[u][i], -bs * t);
+                }
+                d[u][0] = __builtin_fma(cc, d[u][0], -bs * (s[u] * v[u][0]));
+#pragma unroll
+                for (int i = 0; i <= J; ++i) v[u][i] += d[u][i];
             }
-            d[0] = __builtin_fma(cc, d[0], -bs * (s * v[0]));
-#pragma unroll
-            for (int i = 0; i <= J; ++i) v[i] += d[i];
             emit_all(k0 + kk);
         }
     }
 }
 
-template <int J, bool ANG>
+// Workgroups wanted before whole chains are cut into pieces: a few per
+// resident slot on 256 CUs, so the heaviest chains do not form a tail.
+constexpr int64_t kMinWorkgroups = 8192;
+
+template <int J, bool ANG, bool KB, int NPL>
 hipError_t launch(const Plan &plan, const double *r, const double *th, int64_t P, const Planes &o, hipStream_t s)
 {
-    const dim3 grid((unsigned)((P + kBlock - 1) / kBlock), (unsigned)plan.chains.size());
-    hipLaunchKernelGGL((chain_kernel<J, ANG>), grid, dim3(kBlock), 0, s, plan.d_chains, plan.d_coefs,
-                       plan.d_emits, r, th, P, o);
+    const int64_t tiles = (P + (int64_t)kBlock * NPL - 1) / ((int64_t)kBlock * NPL);
+    const bool use_pieces = tiles * (int64_t)plan.chains.size() < kMinWorkgroups;
+    const Chain *list = use_pieces ? plan.d_pieces : plan.d_chains;
+    const size_t count = use_pieces ? plan.pieces.size() : plan.chains.size();
+    const dim3 grid((unsigned)tiles, (unsigned)count);
+    hipLaunchKernelGGL((chain_kernel<J, ANG, KB, NPL>), grid, dim3(kBlock), 0, s, list, plan.d_coefs, plan.d_emits,
+                       r, th, P, o);
     return hipGetLastError();
+}
+
+template <int J, bool ANG>
+hipError_t launch_npl(const Plan &plan, const double *r, const double *th, int64_t P, const Planes &o, hipStream_t s)
+{
+    bool all_f64 = true;
+    for (int q = 0; q < 5; ++q)
+        if (o.plane[q] && o.fmt[q] != F64) all_f64 = false;
+    if (all_f64 && (o.ld % 2) == 0) return launch<J, ANG, false, 2>(plan, r, th, P, o, s);
+    return launch<J, ANG, false, 1>(plan, r, th, P, o, s);
 }
 
 } // namespace
@@ -224,19 +318,23 @@ zp_status launch_chain_kernel(const Plan &plan, const double *d_r, const double 
     if (P <= 0 || plan.chains.empty()) return ZP_OK;
     if ((P + kBlock - 1) / kBlock > (int64_t)INT_MAX) return set_error(ZP_ERR_ARG, "too many points for one launch");
     hipError_t e;
-    if (angular) {
+    if (out.kb) { // series forward: Z (+ dZ/dr for the cache) and the k-blocked copy
+        if (!angular || J > 1) return set_error(ZP_ERR_ARG, "internal: k-blocked output needs the basis, J <= 1");
+        e = J == 0 ? launch<0, true, true, 1>(plan, d_r, d_theta, P, out, s)
+                   : launch<1, true, true, 1>(plan, d_r, d_theta, P, out, s);
+    } else if (angular) {
         switch (J) {
-        case 0: e = launch<0, true>(plan, d_r, d_theta, P, out, s); break;
-        case 1: e = launch<1, true>(plan, d_r, d_theta, P, out, s); break;
-        case 2: e = launch<2, true>(plan, d_r, d_theta, P, out, s); break;
-        default: e = launch<3, true>(plan, d_r, d_theta, P, out, s); break;
+        case 0: e = launch_npl<0, true>(plan, d_r, d_theta, P, out, s); break;
+        case 1: e = launch_npl<1, true>(plan, d_r, d_theta, P, out, s); break;
+        case 2: e = launch_npl<2, true>(plan, d_r, d_theta, P, out, s); break;
+        default: e = launch_npl<3, true>(plan, d_r, d_theta, P, out, s); break;
         }
     } else {
         switch (J) {
-        case 0: e = launch<0, false>(plan, d_r, nullptr, P, out, s); break;
-        case 1: e = launch<1, false>(plan, d_r, nullptr, P, out, s); break;
-        case 2: e = launch<2, false>(plan, d_r, nullptr, P, out, s); break;
-        default: e = launch<3, false>(plan, d_r, nullptr, P, out, s); break;
+        case 0: e = launch_npl<0, false>(plan, d_r, nullptr, P, out, s); break;
+        case 1: e = launch_npl<1, false>(plan, d_r, nullptr, P, out, s); break;
+        case 2: e = launch_npl<2, false>(plan, d_r, nullptr, P, out, s); break;
+        default: e = launch_npl<3, false>(plan, d_r, nullptr, P, out, s); break;
         }
     }
     return hip_check(e, "chain_kernel launch");

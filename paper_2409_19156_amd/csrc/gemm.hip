@@ -1,7 +1,7 @@
 // MFMA contractions for the Zernike series on gfx950, plus the small
 // conversion and fixed-order reduction kernels around them.
 //
-// C(i,j) = sum_k A(i,k) B(k,j) with a 256-thread workgroup (2 x 2 waves) per
+// C(i,j) = sum_k A(i,k) B(k,j) with a 512-thread workgroup (2 x 4 waves) per
 // BM x BN output tile.  Operands come from zero-padded buffers (every
 // dimension a multiple of kPad), so tile loads need no bounds checks; stores
 // are masked to the true output size.  Each operand tile is copied into LDS
@@ -41,7 +41,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 512; // eight waves per workgroup
 constexpr int kFlush = 128;
 
 template <int CT> struct CTr;
@@ -58,31 +58,48 @@ template <> struct CTr<CT_BF3> {
     static constexpr int NP = 3, PK = 8;
 };
 
-// LDS geometry of one operand tile (X rows of the output index by BK).
-template <int CT, int X, int BK, bool KC> struct Tile {
+// LDS geometry and global->LDS copy of one operand tile (X rows of the output
+// index by BK).  LDS holds the tile either as [X][BK+PK] (k contiguous: the
+// k-contiguous and k-blocked layouts, and every bf16 operand) or as
+// [BK][X+16] (x contiguous).  Pads keep the fragment reads conflict-free.
+template <int CT, int X, int BK, int LAY> struct Tile {
     using T = typename CTr<CT>::T;
-    static constexpr bool ROWS_X = KC || CT == CT_BF3; // LDS [X][BK+PK], else [BK][X+16]
+    static constexpr bool ROWS_X = LAY != LAY_XC || CT == CT_BF3;
     static constexpr int STRIDE = ROWS_X ? BK + CTr<CT>::PK : X + 16;
     static constexpr int ELEMS = (ROWS_X ? X : BK) * STRIDE;
     static constexpr int VEC = 16 / (int)sizeof(T);
-    static constexpr int GROWS = KC ? X : BK; // global tile rows
-    static constexpr int GCOLS = KC ? BK : X; // global tile contiguous columns
+    // global tile as GROWS rows of GCOLS contiguous elements
+    static constexpr int GROWS = LAY == LAY_KC ? X : LAY == LAY_XC ? BK : BK / VEC;
+    static constexpr int GCOLS = LAY == LAY_KC ? BK : LAY == LAY_XC ? X : X * VEC;
     static constexpr int NV = GROWS * GCOLS / VEC;
     static constexpr int PER = NV / kThreads;
     static_assert(NV % kThreads == 0, "tile not divisible among threads");
+    static_assert(LAY != LAY_KB8 || VEC == 8, "k-blocked layout is for bf16 operands");
 
     using Regs = u4[PER][CTr<CT>::NP];
 
-    // Global -> registers for the tile whose output-index origin is x0 and k origin k0.
+    static __device__ __forceinline__ void coords(int v, int &gr, int &gc)
+    {
+        const int idx = v * kThreads + (int)threadIdx.x;
+        gr = idx / (GCOLS / VEC);
+        gc = (idx % (GCOLS / VEC)) * VEC;
+    }
+
+    // Global -> registers for the tile at output-index origin x0, k origin k0.
     static __device__ __forceinline__ void load(Regs &reg, const T *base, int64_t ld, int64_t sub, int64_t x0,
                                                 int64_t k0)
     {
 #pragma unroll
         for (int v = 0; v < PER; ++v) {
-            const int idx = v * kThreads + (int)threadIdx.x;
-            const int gr = idx / (GCOLS / VEC);
-            const int gc = (idx % (GCOLS / VEC)) * VEC;
-            const int64_t off = KC ? (x0 + gr) * ld + (k0 + gc) : (k0 + gr) * ld + (x0 + gc);
+            int gr, gc;
+            coords(v, gr, gc);
+            int64_t off;
+            if (LAY == LAY_KC)
+                off = (x0 + gr) * ld + (k0 + gc);
+            else if (LAY == LAY_XC)
+                off = (k0 + gr) * ld + (x0 + gc);
+            else // gr = k block within the tile, gc / 8 = x within the tile
+                off = ((k0 / 8 + gr) * ld + x0) * 8 + gc;
 #pragma unroll
             for (int p = 0; p < CTr<CT>::NP; ++p) reg[v][p] = *(const u4 *)(base + off + p * sub);
         }
@@ -93,14 +110,15 @@ template <int CT, int X, int BK, bool KC> struct Tile {
     {
 #pragma unroll
         for (int v = 0; v < PER; ++v) {
-            const int idx = v * kThreads + (int)threadIdx.x;
-            const int gr = idx / (GCOLS / VEC);
-            const int gc = (idx % (GCOLS / VEC)) * VEC;
+            int gr, gc;
+            coords(v, gr, gc);
 #pragma unroll
             for (int p = 0; p < CTr<CT>::NP; ++p) {
                 T *L = lds + p * ELEMS;
-                if (KC || !ROWS_X) {
+                if (LAY == LAY_KC || !ROWS_X) {
                     *(u4 *)(L + gr * STRIDE + gc) = reg[v][p];
+                } else if (LAY == LAY_KB8) {
+                    *(u4 *)(L + (gc / 8) * STRIDE + gr * 8) = reg[v][p];
                 } else { // bf16 operand contiguous along x: transpose into [x][k]
                     const u4 w = reg[v][p];
 #pragma unroll
@@ -119,17 +137,32 @@ __device__ __forceinline__ typename TL::T frag1(const typename TL::T *L, int x, 
     return TL::ROWS_X ? L[x * TL::STRIDE + k] : L[k * TL::STRIDE + x];
 }
 
-template <int CT, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, int EPI>
+// Tile configuration per element type: BM x BN workgroup tile of eight
+// WM x WN wave tiles (two waves per SIMD), BK k per LDS stage.
+template <int CT> struct Cfg;
+template <> struct Cfg<CT_F64> {
+    static constexpr int BM = 128, BN = 128, BK = 16, WM = 64, WN = 32;
+};
+template <> struct Cfg<CT_F32> {
+    static constexpr int BM = 128, BN = 128, BK = 32, WM = 64, WN = 32;
+};
+template <> struct Cfg<CT_BF3> {
+    static constexpr int BM = 128, BN = 128, BK = 32, WM = 64, WN = 32;
+};
+
+template <int CT, int ALAY, int BLAY, int EPI>
 __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc g)
 {
+    using C = Cfg<CT>;
+    constexpr int BM = C::BM, BN = C::BN, BK = C::BK, WM = C::WM, WN = C::WN;
     using TR = CTr<CT>;
     using T = typename TR::T;
-    using TA = Tile<CT, BM, BK, AKC>;
-    using TB = Tile<CT, BN, BK, BKC>;
+    using TA = Tile<CT, BM, BK, ALAY>;
+    using TB = Tile<CT, BN, BK, BLAY>;
     constexpr int NP = TR::NP;
     constexpr int FM = WM / 16, FN = WN / 16;
     constexpr bool MIXED = CT != CT_F64;
-    static_assert((BM / WM) * (BN / WN) == 4, "four waves per workgroup");
+    static_assert((BM / WM) * (BN / WN) * 64 == kThreads, "one wave tile per wave");
 
     __shared__ __attribute__((aligned(16))) T As[2][NP * TA::ELEMS];
     __shared__ __attribute__((aligned(16))) T Bs[2][NP * TB::ELEMS];
@@ -138,14 +171,30 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc g)
     const int wave = threadIdx.x >> 6;
     const int wm0 = (wave % (BM / WM)) * WM;
     const int wn0 = (wave / (BM / WM)) * WN;
-    const int64_t i0 = (int64_t)blockIdx.x * BM;
-    const int64_t j0 = (int64_t)blockIdx.y * BN;
 
-    // k range of this workgroup (split-K along blockIdx.z)
+    // Tile this workgroup computes.  Workgroups are dispatched in linear order
+    // and dealt round-robin to the 8 XCDs, each with its own L2.  Give every
+    // XCD a contiguous range of logical tiles, and order logical tiles split
+    // (slowest), then row tile, then column tile (fastest): the workgroups that
+    // share an A panel then run together on one XCD and read it from its L2.
+    int bx, by, bz;
+    {
+        const int64_t nx = gridDim.x, ny = gridDim.y;
+        const int64_t total = nx * ny * (int64_t)gridDim.z;
+        const int64_t id = blockIdx.x + nx * (blockIdx.y + ny * (int64_t)blockIdx.z);
+        const int64_t t8 = total / 8 * 8;
+        const int64_t lid = id < t8 ? (id % 8) * (t8 / 8) + id / 8 : id;
+        by = (int)(lid % ny);
+        bx = (int)((lid / ny) % nx);
+        bz = (int)(lid / (ny * nx));
+    }
+    const int64_t i0 = (int64_t)bx * BM;
+    const int64_t j0 = (int64_t)by * BN;
+
+    // k range of this workgroup (split-K along the third grid dimension)
     const int64_t kchunk = g.K / g.splits;
-    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
-    const int64_t kend = kbeg + kchunk;
-    const int ntiles = (int)((kend - kbeg) / BK);
+    const int64_t kbeg = (int64_t)bz * kchunk;
+    const int ntiles = (int)(kchunk / BK);
 
     using Acc = typename std::conditional<CT == CT_F64, d4, f4>::type;
     Acc acc[FM][FN];
@@ -176,52 +225,63 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc g)
     const T *a_base = (const T *)g.a.base;
     const T *b_base = (const T *)g.b.base;
     const int64_t a_ld = g.a.ld, a_sub = g.a.sub, b_ld = g.b.ld, b_sub = g.b.sub;
-    typename TA::Regs ra;
-    typename TB::Regs rb;
+    // Two register sets.  Step t: tile t+1 (fetched during step t-1) goes from
+    // registers into the free LDS buffer, tile t+2 is fetched, and tile t is
+    // multiplied out of the other buffer, so the LDS writes and the global
+    // loads both overlap the MFMAs; one barrier per step.
+    typename TA::Regs ra[2];
+    typename TB::Regs rb[2];
     if (ntiles > 0) {
-        TA::load(ra, a_base, a_ld, a_sub, i0, kbeg);
-        TB::load(rb, b_base, b_ld, b_sub, j0, kbeg);
-        TA::store(ra, As[0]);
-        TB::store(rb, Bs[0]);
+        TA::load(ra[0], a_base, a_ld, a_sub, i0, kbeg);
+        TB::load(rb[0], b_base, b_ld, b_sub, j0, kbeg);
+        TA::store(ra[0], As[0]);
+        TB::store(rb[0], Bs[0]);
+    }
+    if (ntiles > 1) {
+        TA::load(ra[1], a_base, a_ld, a_sub, i0, kbeg + BK);
+        TB::load(rb[1], b_base, b_ld, b_sub, j0, kbeg + BK);
     }
     __syncthreads();
 
     const int lx = lane & 15, lk = lane >> 4;
-    for (int t = 0; t < ntiles; ++t) {
-        const int cur = t & 1;
-        const bool more = t + 1 < ntiles;
-        if (more) {
-            TA::load(ra, a_base, a_ld, a_sub, i0, kbeg + (int64_t)(t + 1) * BK);
-            TB::load(rb, b_base, b_ld, b_sub, j0, kbeg + (int64_t)(t + 1) * BK);
+    auto step = [&](int t, auto cur_c) {
+        constexpr int cur = decltype(cur_c)::value;
+        if (t + 1 < ntiles) {
+            TA::store(ra[cur ^ 1], As[cur ^ 1]);
+            TB::store(rb[cur ^ 1], Bs[cur ^ 1]);
+        }
+        if (t + 2 < ntiles) {
+            TA::load(ra[cur], a_base, a_ld, a_sub, i0, kbeg + (int64_t)(t + 2) * BK);
+            TB::load(rb[cur], b_base, b_ld, b_sub, j0, kbeg + (int64_t)(t + 2) * BK);
         }
         const T *LA = As[cur];
         const T *LB = Bs[cur];
         if constexpr (CT == CT_BF3) {
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 32) {
-                bf8 fa[FM][3], fb[FN][3];
+                bf8 fa[FM][3];
 #pragma unroll
                 for (int a = 0; a < FM; ++a)
 #pragma unroll
                     for (int p = 0; p < 3; ++p)
                         fa[a][p] = *(const bf8 *)(LA + p * TA::ELEMS + (wm0 + a * 16 + lx) * TA::STRIDE + kk + 8 * lk);
 #pragma unroll
-                for (int b = 0; b < FN; ++b)
+                for (int b = 0; b < FN; ++b) {
+                    bf8 fb[3];
 #pragma unroll
                     for (int p = 0; p < 3; ++p)
-                        fb[b][p] = *(const bf8 *)(LB + p * TB::ELEMS + (wn0 + b * 16 + lx) * TB::STRIDE + kk + 8 * lk);
+                        fb[p] = *(const bf8 *)(LB + p * TB::ELEMS + (wn0 + b * 16 + lx) * TB::STRIDE + kk + 8 * lk);
 #pragma unroll
-                for (int a = 0; a < FM; ++a)
-#pragma unroll
-                    for (int b = 0; b < FN; ++b) {
+                    for (int a = 0; a < FM; ++a) {
                         // small cross products first, the leading one last
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][2], fb[b][0], acc[a][b], 0, 0, 0);
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][1], fb[b][1], acc[a][b], 0, 0, 0);
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][0], fb[b][2], acc[a][b], 0, 0, 0);
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][1], fb[b][0], acc[a][b], 0, 0, 0);
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][0], fb[b][1], acc[a][b], 0, 0, 0);
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][0], fb[b][0], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][2], fb[0], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][1], fb[1], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][0], fb[2], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][1], fb[0], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][0], fb[1], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][0], fb[0], acc[a][b], 0, 0, 0);
                     }
+                }
             }
         } else {
 #pragma unroll
@@ -243,11 +303,11 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc g)
             }
         }
         if (MIXED && ((t + 1) * BK) % kFlush == 0) flush();
-        if (more) {
-            TA::store(ra, As[cur ^ 1]);
-            TB::store(rb, Bs[cur ^ 1]);
-        }
         __syncthreads();
+    };
+    for (int t = 0; t < ntiles; t += 2) {
+        step(t, std::integral_constant<int, 0>{});
+        if (t + 1 < ntiles) step(t + 1, std::integral_constant<int, 1>{});
     }
     flush();
 
@@ -262,7 +322,7 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc g)
     };
 
     if constexpr (EPI == EPI_STORE || EPI == EPI_PARTIAL) {
-        double *C = g.C + (EPI == EPI_PARTIAL ? (int64_t)blockIdx.z * g.M * g.ldc : 0);
+        double *Cp = g.C + (EPI == EPI_PARTIAL ? (int64_t)bz * g.M * g.ldc : 0);
 #pragma unroll
         for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -271,85 +331,108 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc g)
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int64_t i = i0 + wm0 + a * 16 + row_of(t);
-                    if (i < g.M && j < g.N) C[i * g.ldc + j] = value(a, b, t);
+                    if (i < g.M && j < g.N) Cp[i * g.ldc + j] = value(a, b, t);
                 }
             }
     } else { // EPI_ROWDOT
+        // Each lane holds 16 rows (4 fragments x 4 accumulator elements) of
+        // 16 columns' products h * d; the 16 lanes sharing those rows (lane
+        // bits 0-3) hold the other columns.  A butterfly reduce-scatter over
+        // lane bits 3..0 sums each row across the 16 lanes in 15 exchanges per
+        // output (every lane ends with the total of one row); waves that share
+        // rows are then added in a fixed order through LDS.
         constexpr int WCOLS = BN / WN;
+        static_assert(FM * 4 == 16, "row-dot epilogue expects 16 rows per lane");
         __shared__ double red[2][WCOLS][BM];
         const int wcol = wave / (BM / WM);
+        using DT = typename std::conditional<CT == CT_F64, double, float>::type;
+        const DT *D1 = (const DT *)g.D1;
+        const DT *D2 = (const DT *)g.D2;
+        double v1[16], v2[16];
 #pragma unroll
         for (int a = 0; a < FM; ++a)
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const int il = wm0 + a * 16 + row_of(t);
-                const int64_t i = i0 + il;
+                const int64_t i = i0 + wm0 + a * 16 + row_of(t);
                 double s1 = 0.0, s2 = 0.0;
 #pragma unroll
                 for (int b = 0; b < FN; ++b) {
                     const int64_t j = j0 + wn0 + b * 16 + lx;
                     if (i < g.M && j < g.N) {
                         const int64_t o = j * g.ldd + i;
-                        const double d1 = g.d_f32 ? (double)((const float *)g.D1)[o] : ((const double *)g.D1)[o];
-                        const double d2 = g.d_f32 ? (double)((const float *)g.D2)[o] : ((const double *)g.D2)[o];
                         const double h = value(a, b, t);
-                        s1 = __builtin_fma(h, d1, s1);
-                        s2 = __builtin_fma(h, d2, s2);
+                        s1 = __builtin_fma(h, (double)D1[o], s1);
+                        s2 = __builtin_fma(h, (double)D2[o], s2);
                     }
                 }
-#pragma unroll
-                for (int m = 1; m < 16; m <<= 1) {
-                    s1 += __shfl_xor(s1, m);
-                    s2 += __shfl_xor(s2, m);
-                }
-                if (lx == 0) {
-                    red[0][wcol][il] = s1;
-                    red[1][wcol][il] = s2;
-                }
+                v1[a * 4 + t] = s1;
+                v2[a * 4 + t] = s2;
             }
+#pragma unroll
+        for (int half = 8; half >= 1; half >>= 1) {
+            const bool upper = (lx & half) != 0;
+#pragma unroll
+            for (int k = 0; k < half; ++k) {
+                const double send1 = upper ? v1[k] : v1[k + half];
+                const double send2 = upper ? v2[k] : v2[k + half];
+                const double keep1 = upper ? v1[k + half] : v1[k];
+                const double keep2 = upper ? v2[k + half] : v2[k];
+                v1[k] = keep1 + __shfl_xor(send1, half);
+                v2[k] = keep2 + __shfl_xor(send2, half);
+            }
+        }
+        // lane lx now holds the row whose 4-bit index (a*4 + t) equals lx
+        {
+            const int r16 = lx;
+            const int il = wm0 + (r16 >> 2) * 16 + row_of(r16 & 3);
+            red[0][wcol][il] = v1[0];
+            red[1][wcol][il] = v2[0];
+        }
         __syncthreads();
         for (int e = threadIdx.x; e < 2 * BM; e += kThreads) {
             const int o = e / BM, il = e % BM;
             const int64_t i = i0 + il;
             if (i >= g.M) continue;
-            double s = 0.0;
+            double sum = 0.0;
 #pragma unroll
-            for (int c = 0; c < WCOLS; ++c) s += red[o][c][il];
-            g.part[((int64_t)blockIdx.y * 2 + o) * g.M + i] = s;
+            for (int c = 0; c < WCOLS; ++c) sum += red[o][c][il];
+            g.part[((int64_t)by * 2 + o) * g.M + i] = sum;
         }
     }
 }
 
-// Tile configurations.
-template <int CT> struct Cfg;
-template <> struct Cfg<CT_F64> {
-    static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32;
-};
-template <> struct Cfg<CT_F32> {
-    static constexpr int BM = 64, BN = 64, BK = 32, WM = 32, WN = 32;
-};
-template <> struct Cfg<CT_BF3> {
-    static constexpr int BM = 64, BN = 64, BK = 32, WM = 32, WN = 32;
-};
-
-template <int CT, bool AKC, bool BKC, int EPI>
+template <int CT, int ALAY, int BLAY, int EPI>
 hipError_t launch_t(const GemmDesc &g, hipStream_t s)
 {
     using C = Cfg<CT>;
     const dim3 grid((unsigned)((g.M + C::BM - 1) / C::BM), (unsigned)((g.N + C::BN - 1) / C::BN),
                     (unsigned)g.splits);
-    hipLaunchKernelGGL((gemm_kernel<CT, C::BM, C::BN, C::BK, C::WM, C::WN, AKC, BKC, EPI>), grid, dim3(kThreads), 0,
-                       s, g);
+    hipLaunchKernelGGL((gemm_kernel<CT, ALAY, BLAY, EPI>), grid, dim3(kThreads), 0, s, g);
     return hipGetLastError();
 }
 
+// The operand-layout combinations the series uses (anything else is an
+// internal error).
 template <int CT, int EPI>
 hipError_t launch_e(const GemmDesc &g, hipStream_t s)
 {
-    if (g.a.kc && g.b.kc) return launch_t<CT, true, true, EPI>(g, s);
-    if (g.a.kc && !g.b.kc) return launch_t<CT, true, false, EPI>(g, s);
-    if (!g.a.kc && g.b.kc) return launch_t<CT, false, true, EPI>(g, s);
-    return launch_t<CT, false, false, EPI>(g, s);
+    const int a = g.a.lay, b = g.b.lay;
+    if constexpr (EPI == EPI_STORE) {
+        if constexpr (CT == CT_BF3) {
+            if (a == LAY_KB8 && b == LAY_KC) return launch_t<CT, LAY_KB8, LAY_KC, EPI>(g, s);
+        } else {
+            if (a == LAY_XC && b == LAY_XC) return launch_t<CT, LAY_XC, LAY_XC, EPI>(g, s);
+        }
+    } else if constexpr (EPI == EPI_PARTIAL) {
+        if constexpr (CT == CT_BF3) {
+            if (a == LAY_KC && b == LAY_KC) return launch_t<CT, LAY_KC, LAY_KC, EPI>(g, s);
+        } else {
+            if (a == LAY_KC && b == LAY_XC) return launch_t<CT, LAY_KC, LAY_XC, EPI>(g, s);
+        }
+    } else {
+        if (a == LAY_KC && b == LAY_KC) return launch_t<CT, LAY_KC, LAY_KC, EPI>(g, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <int CT>
@@ -423,6 +506,45 @@ __global__ __launch_bounds__(256) void convert_t_kernel(const double *__restrict
     }
 }
 
+// dst[c][e] = src[perm[e]][c] for e < R (zero beyond), dst [rows_pad][ldd]:
+// the coefficient matrix transposed with its rows taken in chain-major order.
+__global__ __launch_bounds__(256) void convert_gather_t_kernel(const double *__restrict__ src,
+                                                               const int32_t *__restrict__ perm, int64_t R, int64_t C,
+                                                               int64_t lds, int ct, void *dst, int64_t ldd, int64_t sub)
+{
+    __shared__ double tile[32][33];
+    const int64_t r0 = (int64_t)blockIdx.x * 32; // chain-major rows = dst columns
+    const int64_t c0 = (int64_t)blockIdx.y * 32; // src cols = dst rows
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int y = ty; y < 32; y += 8) {
+        const int64_t r = r0 + y, c = c0 + tx;
+        tile[y][tx] = (r < R && c < C) ? src[(int64_t)perm[r] * lds + c] : 0.0;
+    }
+    __syncthreads();
+    for (int y = ty; y < 32; y += 8) {
+        const int64_t c = c0 + y, r = r0 + tx;
+        put(dst, ct, c * ldd + r, sub, tile[tx][y]);
+    }
+}
+
+// Zero the pad of a k-blocked bf16 operand [Mp/8][ld][8] (three planes, sub
+// apart): every mode e >= M and every point p >= P.
+__global__ void zero_kb8_kernel(uint16_t *dst, int64_t M, int64_t Mp, int64_t P, int64_t ld, int64_t sub)
+{
+    const int64_t total = (Mp / 8) * ld;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t gq = t / ld, p = t % ld;
+        if (gq * 8 + 8 <= M && p < P) continue;
+        for (int q = 0; q < 8; ++q) {
+            if (gq * 8 + q < M && p < P) continue;
+            const int64_t idx = t * 8 + q;
+            dst[idx] = 0;
+            dst[idx + sub] = 0;
+            dst[idx + 2 * sub] = 0;
+        }
+    }
+}
+
 __global__ void zero_kernel(void *dst, int ct, int64_t row0, int64_t rows, int64_t col0, int64_t cols, int64_t ld,
                             int64_t sub)
 {
@@ -477,6 +599,8 @@ zp_status launch_gemm(const GemmDesc &g, hipStream_t s)
     if (g.M <= 0 || g.N <= 0) return ZP_OK;
     if (g.K % kPad != 0 || g.splits < 1 || (g.K / g.splits) % kPad != 0 || g.K / g.splits * g.splits != g.K)
         return set_error(ZP_ERR_ARG, "internal: GEMM K split is not a multiple of the pad");
+    if (g.ct == CT_BF3 ? false : (g.a.lay == LAY_KB8 || g.b.lay == LAY_KB8))
+        return set_error(ZP_ERR_ARG, "internal: k-blocked operands are bf16 only");
     hipError_t e;
     switch (g.ct) {
     case CT_F64: e = launch_c<CT_F64>(g, s); break;
@@ -498,6 +622,21 @@ zp_status launch_convert(const double *src, int64_t R, int64_t C, int64_t lds, i
         hipLaunchKernelGGL(convert_t_kernel, grid, dim3(256), 0, s, src, R, C, lds, ct, dst, ldd, sub);
     }
     return hip_check(hipGetLastError(), "convert launch");
+}
+
+zp_status launch_convert_gather_t(const double *src, const int32_t *perm, int64_t R, int64_t C, int64_t lds,
+                                  int ct, void *dst, int64_t ldd, int64_t rows_pad, int64_t sub, hipStream_t s)
+{
+    const dim3 grid((unsigned)(ldd / 32), (unsigned)(rows_pad / 32));
+    hipLaunchKernelGGL(convert_gather_t_kernel, grid, dim3(256), 0, s, src, perm, R, C, lds, ct, dst, ldd, sub);
+    return hip_check(hipGetLastError(), "convert launch");
+}
+
+zp_status launch_zero_kb8(void *dst, int64_t M, int64_t Mp, int64_t P, int64_t ld, int64_t sub, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_kb8_kernel, dim3(grid_for((Mp / 8) * ld, 256)), dim3(256), 0, s, (uint16_t *)dst, M, Mp,
+                       P, ld, sub);
+    return hip_check(hipGetLastError(), "zero-pad launch");
 }
 
 zp_status launch_zero_pad(void *dst, int ct, int64_t rows, int64_t cols, int64_t rows_pad, int64_t ld, int64_t sub,

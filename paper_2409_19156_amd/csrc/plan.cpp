@@ -93,6 +93,25 @@ std::shared_ptr<Plan> build_plan_host(const int32_t *n, const int32_t *m, int64_
     }
     std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp &x, const Tmp &y) { return x.cost > y.cost; });
     for (auto &t : tmp) plan->chains.push_back(t.c);
+
+    // Pieces of at most kSegEmits emissions, cut on multiples of 8.
+    std::vector<Tmp> pieces;
+    for (const Chain &c : plan->chains) {
+        int e0 = c.emit_off;
+        const int end = c.emit_off + c.emit_cnt;
+        while (e0 < end) {
+            int e1 = std::min(end, (e0 / 8) * 8 + kSegEmits);
+            if (e1 <= e0) e1 = std::min(end, e0 + kSegEmits);
+            Chain p = c;
+            p.emit_off = e0;
+            p.emit_cnt = e1 - e0;
+            p.kmax = plan->emits[e1 - 1].K;
+            pieces.push_back({p, 4.0 * p.emit_cnt + 0.5 * p.kmax});
+            e0 = e1;
+        }
+    }
+    std::stable_sort(pieces.begin(), pieces.end(), [](const Tmp &x, const Tmp &y) { return x.cost > y.cost; });
+    for (auto &t : pieces) plan->pieces.push_back(t.c);
     return plan;
 }
 
@@ -110,23 +129,34 @@ Plan::~Plan()
 
 static zp_status upload(Plan &p)
 {
-    const size_t a = p.chains.size() * sizeof(Chain);
+    // chains and pieces side by side
+    std::vector<Chain> both(p.chains);
+    both.insert(both.end(), p.pieces.begin(), p.pieces.end());
+    const size_t a = both.size() * sizeof(Chain);
     const size_t b = std::max<size_t>(p.coefs.size(), 1) * sizeof(Coef);
     const size_t c = p.emits.size() * sizeof(Emit);
+    const size_t d = p.emits.size() * sizeof(int32_t);
     const size_t off_b = (a + 255) / 256 * 256;
     const size_t off_c = off_b + (b + 255) / 256 * 256;
-    const size_t total = off_c + c;
+    const size_t off_d = off_c + (c + 255) / 256 * 256;
+    const size_t total = off_d + d;
     std::vector<unsigned char> host(total, 0);
-    std::copy_n((const unsigned char *)p.chains.data(), a, host.data());
+    std::copy_n((const unsigned char *)both.data(), a, host.data());
     if (!p.coefs.empty()) std::copy_n((const unsigned char *)p.coefs.data(), p.coefs.size() * sizeof(Coef), host.data() + off_b);
     std::copy_n((const unsigned char *)p.emits.data(), c, host.data() + off_c);
+    for (size_t e = 0; e < p.emits.size(); ++e) {
+        const int32_t col = p.emits[e].col;
+        std::copy_n((const unsigned char *)&col, sizeof col, host.data() + off_d + e * sizeof(int32_t));
+    }
     zp_status st = hip_check(hipMalloc(&p.dmem, total), "hipMalloc(plan)");
     if (st != ZP_OK) return st;
     st = hip_check(hipMemcpy(p.dmem, host.data(), total, hipMemcpyHostToDevice), "hipMemcpy(plan)");
     if (st != ZP_OK) return st;
     p.d_chains = (const Chain *)p.dmem;
+    p.d_pieces = p.d_chains + p.chains.size();
     p.d_coefs = (const Coef *)((unsigned char *)p.dmem + off_b);
     p.d_emits = (const Emit *)((unsigned char *)p.dmem + off_c);
+    p.d_perm = (const int32_t *)((unsigned char *)p.dmem + off_d);
     return ZP_OK;
 }
 

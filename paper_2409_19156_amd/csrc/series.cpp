@@ -15,6 +15,7 @@
 //      grad_r[p] = sum_k H[p][k] dZ_k/dr(p), grad_theta likewise; H is never
 //      stored.  Per-tile partial sums are reduced in a fixed order.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 
 #include "series.hpp"
@@ -46,22 +47,42 @@ struct CacheLayout {
     }
 };
 
-// Split-K count for grad_c: enough workgroups to fill the chip.
+// Split-K count for grad_c: enough workgroups to fill the chip several times,
+// preferring a count that is a whole number of waves over the 256 CUs (one
+// workgroup per CU at a time), each split a whole number of pads.
 int splits_for(int64_t M, int64_t B, int64_t Kp, int ct)
 {
-    const int64_t tiles = ((M + 63) / 64) * ((B + 63) / 64);
-    int64_t s = std::max<int64_t>(1, (1024 + tiles - 1) / tiles);
-    s = std::min<int64_t>(s, Kp / kPad);
-    while (s > 1 && (Kp % (s * kPad)) != 0) --s; // each split a whole number of pads
     (void)ct;
-    return (int)s;
+    const int64_t tiles = ((M + 127) / 128) * ((B + 127) / 128);
+    const int64_t units = Kp / kPad;
+    int best = 1;
+    double best_eff = 0.0;
+    for (int64_t s = 1; s <= units && s <= 64; ++s) {
+        if (units % s) continue;
+        const int64_t wgs = tiles * s;
+        const double waves = (double)wgs / 256.0;
+        const double eff = waves / std::ceil(waves);   // occupancy of the last wave
+        const double score = eff * std::min(1.0, waves / 4.0); // and enough waves
+        if (score > best_eff + 1e-9) {
+            best_eff = score;
+            best = (int)s;
+        }
+    }
+    return best;
 }
 
 // Workspace for one chunk of Pc points.
+//   c      : coefficients in the contraction type, [Mp][Bp]; for the bf16
+//            forward transposed and in chain-major mode order, [Bp][Mp]
+//   z      : the chunk's basis in the contraction type (forward: k-blocked for
+//            bf16, [Mp][Pcp] otherwise; backward without a cache: [Mp][Pcp])
+//   zr, zt : dZ/dr, dZ/dtheta of the chunk (backward without a cache)
+//   g, gt  : the chunk's upstream gradient [Pcp][Bp] (and [Bp][Pcp] for bf16)
+//   pc, pr : split-K partials of dL/dc and row-dot partials of dL/dr, dL/dtheta
 struct WsLayout {
     int64_t Mp, Bp, Pcp;
     int S, T;
-    size_t c_off, ct_off, z_off, zr_off, zt_off, g_off, gt_off, pc_off, pr_off, total;
+    size_t c_off, z_off, zr_off, zt_off, g_off, gt_off, pc_off, pr_off, total;
     WsLayout(int64_t M, int64_t Pc, int64_t B, int ct, bool fwd, bool bwd, bool have_cache)
     {
         Mp = pad_up(M);
@@ -71,27 +92,24 @@ struct WsLayout {
         S = splits_for(M, B, Pcp, ct);
         T = (int)((M + rowdot_bn(ct) - 1) / rowdot_bn(ct));
         size_t o = 0;
-        c_off = o; // c [Mp][Bp]
+        c_off = o;
         o += al(e * (size_t)Mp * (size_t)Bp);
-        ct_off = o; // c^T [Bp][Mp] (bf16 forward)
-        if (ct == CT_BF3 && fwd) o += al(e * (size_t)Bp * (size_t)Mp);
-        z_off = zr_off = zt_off = o;
-        if (!have_cache) {
-            o += al(e * (size_t)Mp * (size_t)Pcp);
-            zr_off = o;
-            if (bwd) o += al(dsize_of(ct) * (size_t)M * (size_t)Pcp);
-            zt_off = o;
-            if (bwd) o += al(dsize_of(ct) * (size_t)M * (size_t)Pcp);
-        }
+        z_off = o;
+        const bool need_z = (fwd && ct == CT_BF3) || !have_cache;
+        if (need_z) o += al(e * (size_t)Mp * (size_t)Pcp);
+        zr_off = o;
+        if (bwd && !have_cache) o += al(dsize_of(ct) * (size_t)M * (size_t)Pcp);
+        zt_off = o;
+        if (bwd && !have_cache) o += al(dsize_of(ct) * (size_t)M * (size_t)Pcp);
         g_off = gt_off = pc_off = pr_off = o;
         if (bwd) {
-            o += al(e * (size_t)Pcp * (size_t)Bp); // g [Pcp][Bp]
+            o += al(e * (size_t)Pcp * (size_t)Bp);
             gt_off = o;
-            if (ct == CT_BF3) o += al(e * (size_t)Bp * (size_t)Pcp); // g^T [Bp][Pcp]
+            if (ct == CT_BF3) o += al(e * (size_t)Bp * (size_t)Pcp);
             pc_off = o;
-            o += al(8 * (size_t)S * (size_t)M * (size_t)B); // grad_c split-K partials
+            o += al(8 * (size_t)S * (size_t)M * (size_t)B);
             pr_off = o;
-            o += al(8 * (size_t)T * 2 * (size_t)Pc); // row-dot partials
+            o += al(8 * (size_t)T * 2 * (size_t)Pc);
         }
         total = o;
     }
@@ -121,7 +139,8 @@ zp_status common_checks(const int32_t *n, const int32_t *m, int64_t M, int64_t P
     return ZP_OK;
 }
 
-// Basis of points [p0, p0+Pc) into the given planes (Z in type ct, derivative planes in dsize).
+// Basis of points [p0, p0+Pc) into [Mp][ld] planes: Z in the contraction type
+// (pad zeroed), dZ/dr and dZ/dtheta (if not null) in FP64 / FP32.
 zp_status basis_into(const Plan &plan, const double *r, const double *th, int64_t p0, int64_t Pc, int ct,
                      void *z, void *zr, void *zt, int64_t ld, int64_t Mp, int64_t M, hipStream_t s)
 {
@@ -185,44 +204,67 @@ zp_status zp_series_fwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
     const WsLayout L(M, Pc, B, ct, true, false, have_cache);
     char *ws = (char *)d_ws;
     const int64_t Mp = L.Mp, Bp = L.Bp;
-    // c in the layout the forward's B operand wants: k (modes) contiguous for bf16.
-    void *cbuf = ws + (ct == CT_BF3 ? L.ct_off : L.c_off);
-    if (ct == CT_BF3)
-        st = launch_convert(d_c, M, B, B, ct, cbuf, Mp, Bp, Bp * Mp, true, s);
-    else
+    void *cbuf = ws + L.c_off;
+    if (ct == CT_BF3) // B(k = e, j = b) = c[perm[e]][b], k-contiguous
+        st = launch_convert_gather_t(d_c, plan->d_perm, M, B, B, ct, cbuf, Mp, Bp, Bp * Mp, s);
+    else // B(k = q, j = b) = c[q][b]
         st = launch_convert(d_c, M, B, B, ct, cbuf, Bp, Mp, Mp * Bp, false, s);
     if (st != ZP_OK) return st;
 
     const CacheLayout CL(M, P, ct);
+    char *cache = (char *)d_cache;
+    const size_t esz = ct == CT_BF3 ? 2 : ct_bytes(ct);
     if (have_cache) {
-        char *cache = (char *)d_cache;
-        st = basis_into(*plan, d_r, d_theta, 0, P, ct, cache + CL.z_off, cache + CL.zr_off, cache + CL.zt_off, CL.Pp,
-                        Mp, M, s);
+        st = launch_zero_pad(cache + CL.z_off, ct, M, P, Mp, CL.Pp, Mp * CL.Pp, s);
         if (st != ZP_OK) return st;
     }
     for (int64_t p0 = 0; p0 < P; p0 += Pc) {
         const int64_t pc = std::min(Pc, P - p0);
-        const void *z;
-        int64_t ldz, zsub;
-        if (have_cache) {
-            z = (const char *)d_cache + CL.z_off + ct_bytes(ct) / (ct == CT_BF3 ? 3 : 1) * (size_t)p0;
-            ldz = CL.Pp;
-            zsub = Mp * CL.Pp;
-        } else {
-            const int64_t pcp = pad_up(pc);
-            st = basis_into(*plan, d_r, d_theta, p0, pc, ct, ws + L.z_off, nullptr, nullptr, pcp, Mp, M, s);
+        const int64_t pcp = pad_up(pc);
+        Planes o{};
+        const int zfmt = ct == CT_F64 ? F64 : ct == CT_F32 ? F32 : B16X3;
+        const int dfmt = ct == CT_F64 ? F64 : F32;
+        int J = 0;
+        if (have_cache) { // keep Z, dZ/dr, dZ/dtheta for the backward
+            o.ld = CL.Pp;
+            o.sub = Mp * CL.Pp;
+            o.plane[0] = cache + CL.z_off + esz * (size_t)p0;
+            o.fmt[0] = zfmt;
+            o.plane[1] = cache + CL.zr_off + dsize_of(ct) * (size_t)p0;
+            o.fmt[1] = dfmt;
+            o.plane[4] = cache + CL.zt_off + dsize_of(ct) * (size_t)p0;
+            o.fmt[4] = dfmt;
+            J = 1;
+        } else if (ct != CT_BF3) {
+            o.ld = pcp;
+            o.sub = Mp * pcp;
+            o.plane[0] = ws + L.z_off;
+            o.fmt[0] = zfmt;
+            st = launch_zero_pad(ws + L.z_off, ct, M, pc, Mp, pcp, Mp * pcp, s);
             if (st != ZP_OK) return st;
-            z = ws + L.z_off;
-            ldz = pcp;
-            zsub = Mp * pcp;
         }
+        if (ct == CT_BF3) {
+            o.kb = ws + L.z_off;
+            o.kb_ld = pcp;
+            o.kb_sub = Mp * pcp;
+            st = launch_zero_kb8(o.kb, M, Mp, pc, pcp, Mp * pcp, s);
+            if (st != ZP_OK) return st;
+        }
+        st = launch_chain_kernel(*plan, d_r + p0, d_theta + p0, pc, J, true, o, s);
+        if (st != ZP_OK) return st;
+
         GemmDesc g{};
         g.ct = ct;
-        g.a = Operand{z, ldz, zsub, false}; // A(i=p, k=q) = Z[q][p]
-        if (ct == CT_BF3)
-            g.b = Operand{cbuf, Mp, Bp * Mp, true}; // B(k=q, j=b) = c^T[b][q]
-        else
-            g.b = Operand{cbuf, Bp, Mp * Bp, false}; // B(k=q, j=b) = c[q][b]
+        if (ct == CT_BF3) {
+            g.a = Operand{ws + L.z_off, pcp, Mp * pcp, LAY_KB8}; // A(i = p, k = e)
+            g.b = Operand{cbuf, Mp, Bp * Mp, LAY_KC};            // B(k = e, j = b)
+        } else if (have_cache) {
+            g.a = Operand{cache + CL.z_off + esz * (size_t)p0, CL.Pp, Mp * CL.Pp, LAY_XC}; // A(i = p, k = q) = Z[q][p]
+            g.b = Operand{cbuf, Bp, Mp * Bp, LAY_XC};
+        } else {
+            g.a = Operand{ws + L.z_off, pcp, Mp * pcp, LAY_XC};
+            g.b = Operand{cbuf, Bp, Mp * Bp, LAY_XC};
+        }
         g.M = pc;
         g.N = B;
         g.K = Mp;
@@ -301,11 +343,11 @@ zp_status zp_series_bwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
         if (d_grad_c) {
             GemmDesc g{};
             g.ct = ct;
-            g.a = Operand{z, ldz, zsub, true}; // A(i=q, k=p) = Z[q][p]
+            g.a = Operand{z, ldz, zsub, LAY_KC}; // A(i=q, k=p) = Z[q][p]
             if (ct == CT_BF3)
-                g.b = Operand{ws + L.gt_off, pcp, Bp * pcp, true}; // B(k=p, j=b) = g^T[b][p]
+                g.b = Operand{ws + L.gt_off, pcp, Bp * pcp, LAY_KC}; // B(k=p, j=b) = g^T[b][p]
             else
-                g.b = Operand{gbuf, Bp, pcp * Bp, false}; // B(k=p, j=b) = g[p][b]
+                g.b = Operand{gbuf, Bp, pcp * Bp, LAY_XC}; // B(k=p, j=b) = g[p][b]
             g.M = M;
             g.N = B;
             g.K = pcp;
@@ -321,8 +363,8 @@ zp_status zp_series_bwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
         if (need_rt) {
             GemmDesc g{};
             g.ct = ct;
-            g.a = Operand{gbuf, Bp, pcp * Bp, true};  // A(i=p, k=b) = g[p][b]
-            g.b = Operand{cbuf, Bp, Mp * Bp, true};   // B(k=b, j=q) = c[q][b]
+            g.a = Operand{gbuf, Bp, pcp * Bp, LAY_KC}; // A(i=p, k=b) = g[p][b]
+            g.b = Operand{cbuf, Bp, Mp * Bp, LAY_KC};  // B(k=b, j=q) = c[q][b]
             g.M = pc;
             g.N = M;
             g.K = Bp;

@@ -17,14 +17,19 @@ inline size_t ct_bytes(int ct) { return ct == CT_F64 ? 8 : ct == CT_F32 ? 4 : 6;
 constexpr int64_t kPad = 128;
 inline int64_t pad_up(int64_t x) { return (x + kPad - 1) / kPad * kPad; }
 
-// Operand of C(i,j) = sum_k A(i,k) B(k,j).  `kc` true: contiguous along k
-// (element (x,k) at base[x*ld + k]); false: contiguous along the other index
-// (element (x,k) at base[k*ld + x]).  `sub` separates the BF3 planes.
+// Memory layout of a GEMM operand, element (x, k) where x is the operand's
+// output index (i for A, j for B):
+//   LAY_KC  : base[x*ld + k]                      (contiguous along k)
+//   LAY_XC  : base[k*ld + x]                      (contiguous along x)
+//   LAY_KB8 : base[((k/8)*ld + x)*8 + k%8]        (k in blocks of eight)
+enum Layout : int { LAY_KC = 0, LAY_XC = 1, LAY_KB8 = 2 };
+
+// Operand of C(i,j) = sum_k A(i,k) B(k,j); `sub` separates the BF3 planes.
 struct Operand {
     const void *base;
     int64_t ld;
     int64_t sub;
-    bool kc;
+    int lay;
 };
 
 enum Epi : int {
@@ -57,6 +62,13 @@ zp_status launch_gemm(const GemmDesc &g, hipStream_t s);
 // row-major FP64 src [R][C] (leading dimension lds); zero padding.
 zp_status launch_convert(const double *src, int64_t R, int64_t C, int64_t lds, int ct, void *dst, int64_t ldd,
                          int64_t rows_pad, int64_t sub, bool transpose, hipStream_t s);
+
+// dst[c][e] = src[perm[e]][c] (e < R, zero padded), dst [rows_pad][ldd].
+zp_status launch_convert_gather_t(const double *src, const int32_t *perm, int64_t R, int64_t C, int64_t lds,
+                                  int ct, void *dst, int64_t ldd, int64_t rows_pad, int64_t sub, hipStream_t s);
+
+// Zero the pad (modes >= M, points >= P) of a k-blocked bf16 operand.
+zp_status launch_zero_kb8(void *dst, int64_t M, int64_t Mp, int64_t P, int64_t ld, int64_t sub, hipStream_t s);
 
 // Zero the pad region of a [rows_pad][ld] compute-type plane set whose
 // valid block is [rows][cols].

@@ -36,6 +36,8 @@ namespace zp {
 // It is an exact algebraic rewrite of the paper's recurrence (the sum rule
 // of its coefficients makes v = 1 at s = 0 a fixed point), so the end point
 // is reproduced exactly and rounding errors vanish with s.
+constexpr int kSegEmits = 16; // emissions per chain piece
+
 struct Chain {
     int32_t alpha;    // |m| of every mode on this chain
     int32_t kmax;     // largest K requested on this chain
@@ -61,14 +63,22 @@ struct Plan {
     int device = -1;
     std::vector<int32_t> n, m; // the key
     std::vector<Chain> chains; // in launch order (most work first)
+    // The same chains cut into pieces of at most kSegEmits emissions (piece
+    // boundaries on multiples of 8 of the emission index).  A piece walks its
+    // chain from k = 0 to its own last K and emits only its range, so it costs
+    // a short recurrence prefix again; the launcher uses pieces when there
+    // are too few point tiles to fill the chip with whole chains.
+    std::vector<Chain> pieces;
     std::vector<Coef> coefs;
     std::vector<Emit> emits;
     int32_t nmax = 0;
     // device copies (one allocation)
     void *dmem = nullptr;
     const Chain *d_chains = nullptr;
+    const Chain *d_pieces = nullptr;
     const Coef *d_coefs = nullptr;
     const Emit *d_emits = nullptr;
+    const int32_t *d_perm = nullptr; // d_perm[e] = emits[e].col: chain-major order -> column
     ~Plan();
 };
 
@@ -91,11 +101,18 @@ enum PlaneFmt : int32_t { F64 = 0, F32 = 1, B16X3 = 2 };
 // d2/dr2, d3/dr3, d/dtheta; null planes are not written.  Column i of a plane
 // starts ld elements after column i-1.  A B16X3 plane is three bf16 planes
 // (hi, mid, lo) sub elements apart.
+// kb, if not null, receives Z once more as three bf16 planes (kb_sub apart) in
+// the k-blocked layout the series forward contracts over: the mode index is
+// the emission index e (chain-major order, see Plan::d_perm) and element
+// (e, p) sits at ((e/8)*kb_ld + p)*8 + e%8.
 struct Planes {
     void *plane[5];
     int64_t ld;
     int64_t sub;
     int32_t fmt[5];
+    void *kb;
+    int64_t kb_ld;
+    int64_t kb_sub;
 };
 
 // Launch the chain kernel: radial only (angular = false) or basis.  J is the

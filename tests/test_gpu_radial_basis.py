@@ -160,3 +160,31 @@ def test_invalid_modes_raise(zp):
         zp.radial([1001], [1], r, 0)
     with pytest.raises(zp.ZpError):
         zp.radial([2], [0], r, 4)
+
+
+def test_largest_supported_order(zp, oracle_mod):
+    """n up to the library maximum (1000), every 25th |m|, orders 0..3, against
+    the oracle with the same per-order tolerance."""
+    ms = np.arange(0, 1001, 25)
+    n = np.array([1000 - (mm % 2) for mm in ms], dtype=np.int32)
+    n = np.concatenate([n, [998, 999]]).astype(np.int32)
+    m = np.concatenate([ms, [0, 1]]).astype(np.int32)
+    rng = np.random.default_rng(1000)
+    r = np.concatenate([rng.random(200), 1 - 10 ** rng.uniform(-8, 0, 40), 10 ** rng.uniform(-8, 0, 40), [0.0, 1.0]])
+    _check_radial(zp, oracle_mod, n, m, r, 3, "n=1000")
+
+
+def test_plan_cache_churn(zp):
+    """More distinct mode lists than the plan cache holds, revisited: every
+    result is bitwise identical to the first evaluation (plans are rebuilt
+    correctly after eviction and after zp_cache_clear)."""
+    from paper_2409_19156_amd import _lib
+
+    r = _dev(np.linspace(0, 1, 300))
+    lists = [W.radial_pairs(k) for k in range(2, 40)]
+    first = [zp.radial(n, m, r, 2).clone() for n, m in lists]
+    for rep in range(2):
+        if rep == 1:
+            _lib.load().zp_cache_clear()
+        for (n, m), ref in zip(reversed(lists), reversed(first)):
+            assert torch.equal(zp.radial(n, m, r, 2), ref)
