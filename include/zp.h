@@ -104,6 +104,19 @@ zp_status zp_basis(const int32_t *h_n, const int32_t *h_m, int64_t M, const doub
                    const double *d_theta, int64_t P, uint32_t mask, double *d_out, void *stream);
 
 /*
+ * zp_radial_direct -- the same outputs as zp_radial, evaluated directly from
+ * the closed form Eq. (radial-part-eq): each term c_s r^(n-2s) (and its
+ * r-derivatives) formed in FP64 and summed in order of s.  This is the
+ * comparator of the paper's accuracy study (Sec. 4): its error grows quickly
+ * with n - |m| (alternating terms of very different size), and for large n
+ * the coefficients overflow FP64 (inf / NaN outputs).  For accuracy
+ * comparisons only; zp_radial is the accurate path.  Arguments and errors as
+ * zp_radial; at most 65535 modes per call.
+ */
+zp_status zp_radial_direct(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r, int64_t P,
+                           int32_t max_dr, double *d_out, void *stream);
+
+/*
  * Zernike series f(r_p, theta_p)_b = sum_k c[k][b] Z_k(r_p, theta_p) for B
  * coefficient sets at once (the basis contracted with coefficients; the
  * paper's use of Zernike polynomials as a spectral basis, Sec. 1 and 3), and
@@ -151,6 +164,25 @@ zp_status zp_series_bwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
                         const double *d_theta, int64_t P, const double *d_c, int64_t B, int32_t prec,
                         const double *d_g, const void *d_cache, double *d_grad_c, double *d_grad_r,
                         double *d_grad_theta, void *d_ws, size_t ws_bytes, void *stream);
+
+/*
+ * zp_series_jvp -- forward-mode derivative (Jacobian-vector product) of
+ * zp_series_fwd along tangents (tc, tr, ttheta) of (c, r, theta):
+ *   tf[p][b] = sum_k Z_k(p) tc[k][b]
+ *            + sum_k (tr[p] dZ_k/dr(p) + ttheta[p] dZ_k/dtheta(p)) c[k][b]
+ * (the paper's forward-mode automatic differentiation, Sec. 3).
+ *   d_tc      nullable device double[M*B]
+ *   d_tr, d_ttheta  nullable device double[P]
+ *   d_c       device double[M*B]; may be NULL when tr and ttheta are both NULL
+ *   d_tf      device double[P*B] (output; all zeros if every tangent is NULL)
+ * The two sums are one contraction over a stacked mode index, in the
+ * precision prec.  Workspace as for zp_series_fwd (zp_series_workspace covers
+ * it).  Errors: as zp_series_fwd.
+ */
+zp_status zp_series_jvp(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r,
+                        const double *d_theta, int64_t P, const double *d_c, int64_t B, int32_t prec,
+                        const double *d_tc, const double *d_tr, const double *d_ttheta, double *d_tf, void *d_ws,
+                        size_t ws_bytes, void *stream);
 
 /* Static description of a status code. */
 const char *zp_status_string(zp_status s);

@@ -17,7 +17,7 @@ from ._lib import ZpError
 Z, DR, DR2, DR3, DTHETA = 1, 2, 4, 8, 16
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
-__all__ = ["radial", "basis", "ZpError", "Z", "DR", "DR2", "DR3", "DTHETA", "PREC", "modes_i32"]
+__all__ = ["radial", "radial_direct", "basis", "ZpError", "Z", "DR", "DR2", "DR3", "DTHETA", "PREC", "modes_i32"]
 
 
 def modes_i32(n, m):
@@ -62,6 +62,22 @@ def radial(n, m, r: torch.Tensor, max_dr: int = 0, out: torch.Tensor | None = No
         st = lib.zp_radial(nh.ctypes.data, mh.ctypes.data, M, r.data_ptr(), P, int(max_dr), out.data_ptr(),
                            _stream(r.device))
     _lib.check(st, "zp_radial")
+    return out
+
+
+def radial_direct(n, m, r: torch.Tensor, max_dr: int = 0) -> torch.Tensor:
+    """Same outputs as ``radial`` but evaluated directly from the closed-form
+    sum in FP64 (the paper's accuracy comparator; loses digits as n - |m|
+    grows).  For accuracy comparisons only."""
+    lib = _lib.load()
+    nh, mh = modes_i32(n, m)
+    r = _points(r, "r")
+    M, P = nh.size, r.numel()
+    out = torch.empty((max_dr + 1, M, P), dtype=torch.float64, device=r.device)
+    with torch.cuda.device(r.device):
+        st = lib.zp_radial_direct(nh.ctypes.data, mh.ctypes.data, M, r.data_ptr(), P, int(max_dr), out.data_ptr(),
+                                  _stream(r.device))
+    _lib.check(st, "zp_radial_direct")
     return out
 
 
@@ -185,8 +201,41 @@ def series_backward(n, m, r, theta, c, g, prec="fp64", cache: torch.Tensor | Non
     return gc, gr, gt
 
 
+def series_jvp(n, m, r, theta, c, tc=None, tr=None, ttheta=None, prec="fp64", ws: torch.Tensor | None = None,
+               mem_budget=None) -> torch.Tensor:
+    """Forward-mode derivative of ``series_forward`` along tangents (tc, tr,
+    ttheta) of (c, r, theta); any tangent may be None."""
+    lib = _lib.load()
+    nh, mh = modes_i32(n, m)
+    r, theta = _points(r, "r"), _points(theta, "theta")
+    M, P = nh.size, r.numel()
+    c = _coef(c, M)
+    B = c.shape[1]
+    tf = torch.empty((P, B), dtype=torch.float64, device=r.device)
+    if tc is not None:
+        tc = _coef(tc, M)
+        if tc.shape != c.shape:
+            raise ValueError("tc must have the shape of c")
+    if tr is not None:
+        tr = _points(tr, "tr")
+    if ttheta is not None:
+        ttheta = _points(ttheta, "ttheta")
+    if M == 0 or P == 0 or B == 0:
+        return tf.zero_()
+    if ws is None:
+        ws = _workspace(M, P, B, prec, _budget(mem_budget), r.device)
+    ptr = (lambda t: t.data_ptr() if t is not None else None)
+    with torch.cuda.device(r.device):
+        st = lib.zp_series_jvp(nh.ctypes.data, mh.ctypes.data, M, r.data_ptr(), theta.data_ptr(), P, c.data_ptr(), B,
+                               _prec_code(prec), ptr(tc), ptr(tr), ptr(ttheta), tf.data_ptr(), ws.data_ptr(),
+                               ws.numel(), _stream(r.device))
+    _lib.check(st, "zp_series_jvp")
+    return tf
+
+
 class ZernikeSeries(torch.autograd.Function):
-    """f = Z(r, theta)^T c with a hand-written adjoint (zp_series_bwd).
+    """f = Z(r, theta)^T c with a hand-written adjoint (zp_series_bwd) and
+    forward-mode rule (zp_series_jvp).
 
     The basis (Z, dZ/dr, dZ/dtheta) is kept from the forward when its size is
     within the memory budget, and recomputed chunk by chunk in the backward
@@ -207,6 +256,7 @@ class ZernikeSeries(torch.autograd.Function):
         ctx.budget = budget
         ctx.cache = cache
         ctx.save_for_backward(c, r, theta)
+        ctx.save_for_forward(c, r, theta)
         return f
 
     @staticmethod
@@ -222,10 +272,16 @@ class ZernikeSeries(torch.autograd.Function):
             gt = gt.view_as(theta)
         return gc, gr, gt, None, None, None, None
 
+    @staticmethod
+    def jvp(ctx, tc, tr, ttheta, *unused):
+        c, r, theta = ctx.saved_tensors
+        nh, mh = ctx.modes
+        return series_jvp(nh, mh, r, theta, c, tc=tc, tr=tr, ttheta=ttheta, prec=ctx.prec, mem_budget=ctx.budget)
+
 
 def series(c, r, theta, n, m, prec="fp64", mem_budget=None):
     """Differentiable Zernike series f[p, b] = sum_k c[k, b] Z_k(r_p, theta_p)."""
     return ZernikeSeries.apply(c, r, theta, n, m, prec, mem_budget)
 
 
-__all__ += ["series_sizes", "series_forward", "series_backward", "ZernikeSeries", "series"]
+__all__ += ["series_sizes", "series_forward", "series_backward", "series_jvp", "ZernikeSeries", "series"]

@@ -17,8 +17,9 @@ STATUS_NAMES = {0: "ZP_OK", 1: "ZP_ERR_MODE", 2: "ZP_ERR_ARG", 3: "ZP_ERR_ORDER"
                 5: "ZP_ERR_HIP", 6: "ZP_ERR_PREC"}
 
 # Every symbol include/zp.h declares.
-EXPORTS = ("zp_radial", "zp_basis", "zp_series_workspace", "zp_series_cache_bytes", "zp_series_fwd",
-           "zp_series_bwd", "zp_status_string", "zp_last_error", "zp_cache_clear", "zp_abi_version")
+EXPORTS = ("zp_radial", "zp_radial_direct", "zp_basis", "zp_series_workspace", "zp_series_cache_bytes", "zp_series_fwd",
+           "zp_series_bwd", "zp_series_jvp", "zp_status_string", "zp_last_error", "zp_cache_clear",
+           "zp_abi_version")
 
 
 class ZpError(RuntimeError):
@@ -41,11 +42,13 @@ def load() -> ctypes.CDLL:
     szp = ctypes.POINTER(ctypes.c_size_t)
     sig = {
         "zp_radial": [vp, vp, i64, vp, i64, i32, vp, vp],
+        "zp_radial_direct": [vp, vp, i64, vp, i64, i32, vp, vp],
         "zp_basis": [vp, vp, i64, vp, vp, i64, u32, vp, vp],
         "zp_series_workspace": [i64, i64, i64, i32, szp, szp],
         "zp_series_cache_bytes": [i64, i64, i32, szp],
         "zp_series_fwd": [vp, vp, i64, vp, vp, i64, vp, i64, i32, vp, vp, vp, sz, vp],
         "zp_series_bwd": [vp, vp, i64, vp, vp, i64, vp, i64, i32, vp, vp, vp, vp, vp, vp, sz, vp],
+        "zp_series_jvp": [vp, vp, i64, vp, vp, i64, vp, i64, i32, vp, vp, vp, vp, vp, sz, vp],
     }
     for name, args in sig.items():
         if not hasattr(lib, name):

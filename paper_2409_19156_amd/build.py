@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libzp.so")
-SOURCES = ["zp_api.cpp", "plan.cpp", "series.cpp", "chain_kernel.hip", "gemm.hip"]
+SOURCES = ["zp_api.cpp", "plan.cpp", "series.cpp", "chain_kernel.hip", "gemm.hip", "direct_kernel.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -63,24 +63,60 @@ __device__ __forceinline__ void split3(double v, uint16_t &h, uint16_t &m, uint1
     l = bf16_rne((float)r2);
 }
 
-__device__ __forceinline__ void store_plane(const Planes &o, int q, int64_t idx, double v)
+__device__ __forceinline__ void store_fmt(void *base, int fmt, int64_t sub, int64_t idx, double v)
 {
-    switch (o.fmt[q]) {
+    switch (fmt) {
     case F64:
-        __builtin_nontemporal_store(v, (double *)o.plane[q] + idx);
+        __builtin_nontemporal_store(v, (double *)base + idx);
         break;
     case F32:
-        __builtin_nontemporal_store((float)v, (float *)o.plane[q] + idx);
+        __builtin_nontemporal_store((float)v, (float *)base + idx);
         break;
     default: { // B16X3
-        uint16_t *b = (uint16_t *)o.plane[q] + idx;
+        uint16_t *b = (uint16_t *)base + idx;
         uint16_t h, md, l;
         split3(v, h, md, l);
         __builtin_nontemporal_store(h, b);
-        __builtin_nontemporal_store(md, b + o.sub);
-        __builtin_nontemporal_store(l, b + 2 * o.sub);
+        __builtin_nontemporal_store(md, b + sub);
+        __builtin_nontemporal_store(l, b + 2 * sub);
         break;
     }
+    }
+}
+
+__device__ __forceinline__ void store_plane(const Planes &o, int q, int64_t idx, double v)
+{
+    store_fmt(o.plane[q], o.fmt[q], o.sub, idx, v);
+}
+
+// One k-blocked bf16 group register (8 emissions x 16 bits per plane); see
+// the kernel for how groups are formed.
+template <int NW>
+__device__ __forceinline__ void kb_push(uint32_t (&w)[NW][4], double val, uint16_t *kb, int64_t kb_sub, int eidx,
+                                        bool full_group)
+{
+    uint16_t hv[3];
+    split3(val, hv[0], hv[1], hv[2]);
+    if (full_group) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            uint32_t *x4 = w[q < NW ? q : 0];
+            x4[0] = __builtin_amdgcn_alignbit(x4[1], x4[0], 16);
+            x4[1] = __builtin_amdgcn_alignbit(x4[2], x4[1], 16);
+            x4[2] = __builtin_amdgcn_alignbit(x4[3], x4[2], 16);
+            x4[3] = (x4[3] >> 16) | ((uint32_t)hv[q] << 16);
+        }
+        if ((eidx & 7) == 7) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const uint32_t *x4 = w[q < NW ? q : 0];
+                const u4 vv = {x4[0], x4[1], x4[2], x4[3]};
+                __builtin_nontemporal_store(vv, (u4 *)(kb + q * kb_sub));
+            }
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) __builtin_nontemporal_store(hv[q], kb + q * kb_sub + (eidx & 7));
     }
 }
 
@@ -100,7 +136,7 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 
 // NPL points per lane (1, or 2 for FP64-only outputs: each store then writes
 // 16 bytes per lane, 1 KB per wave).
-template <int J, bool ANG, bool KB, int NPL>
+template <int J, bool ANG, bool KB, int NPL, bool DIR>
 __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__ chains,
                                                        const Coef *__restrict__ coefs,
                                                        const Emit *__restrict__ emits,
@@ -109,6 +145,7 @@ __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__
                                                        Planes out)
 {
     static_assert(NPL == 1 || (NPL == 2 && !KB), "two points per lane only for plain FP64 planes");
+    static_assert(!DIR || (ANG && J >= 1), "the directional derivative needs the basis and dZ/dr");
     __shared__ Coef tab[kTabChunk];
 
     const Chain ch = chains[blockIdx.y];
@@ -116,12 +153,14 @@ __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__
     const int64_t p0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * NPL;
 
     bool live[NPL], high[NPL];
-    double x[NPL], s[NPL], s1[NPL], s2[NPL], cs[NPL], sn[NPL];
+    double x[NPL], s[NPL], s1[NPL], s2[NPL], cs[NPL], sn[NPL], tr[NPL], tt[NPL];
     double w[NPL][J + 1], v[NPL][J + 1], d[NPL][J + 1];
 #pragma unroll
     for (int u = 0; u < NPL; ++u) {
         live[u] = p0 + u < P;
         x[u] = live[u] ? r[p0 + u] : 0.0;
+        tr[u] = (DIR && live[u] && out.dir_r) ? out.dir_r[p0 + u] : 0.0;  // tangent of r
+        tt[u] = (DIR && live[u] && out.dir_th) ? out.dir_th[p0 + u] : 0.0; // tangent of theta
         // Anchor and s(r), ds/dr, d2s/dr2.
         const double x2 = x[u] * x[u];
         high[u] = !(x2 < 0.5);
@@ -169,7 +208,8 @@ __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__
     // Staging for the k-blocked bf16 copy of Z: a 128-bit shift register per
     // plane collects the eight emissions of a group that lies wholly on this
     // chain piece; groups that straddle a boundary are stored element-wise.
-    uint32_t kbw[KB ? 3 : 1][4] = {};
+    uint32_t kbw[3][4] = {};
+    uint32_t kbd[DIR ? 3 : 1][4] = {};
 
     auto emit_all = [&](int k) {
         while (nextK == k) {
@@ -178,7 +218,7 @@ __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__
             ++e;
             nextK = e < e_end ? emits[e].K : INT_MAX;
             const bool is_sin = em.flags & 1;
-            double val[5][NPL];
+            double val[5][NPL], vdir[NPL];
 #pragma unroll
             for (int u = 0; u < NPL; ++u) {
                 // g^(j) = d^j/dr^j v(s(r))
@@ -203,20 +243,23 @@ __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__
                 // of R sin(|m| theta) = |m| R cos(|m| theta) (m < 0).
                 const double fa = (double)alpha;
                 val[4][u] = ANG ? (is_sin ? fa * R[0] * cs[u] : -fa * R[0] * sn[u]) : 0.0;
+                vdir[u] = DIR ? __builtin_fma(tr[u], val[J >= 1 ? 1 : 0][u], tt[u] * val[4][u]) : 0.0;
             }
             const int64_t idx = (int64_t)em.col * out.ld + p0;
             if (NPL == 2) {
                 // planes are FP64 here; a pair of points is 16 bytes, aligned
                 // because ld and p0 are even
 #pragma unroll
-                for (int q = 0; q < 5; ++q) {
-                    if ((q > J && q < 4) || (q == 4 && !ANG) || !out.plane[q]) continue;
-                    double *dst = (double *)out.plane[q] + idx;
+                for (int q = 0; q < 6; ++q) {
+                    void *base = q < 5 ? out.plane[q] : out.dir;
+                    if ((q > J && q < 4) || (q == 4 && !ANG) || (q == 5 && !DIR) || !base) continue;
+                    const double *vq = q < 5 ? val[q] : vdir;
+                    double *dst = (double *)base + idx;
                     if (live[NPL - 1]) {
-                        const d2 pair = {val[q][0], val[q][NPL - 1]};
+                        const d2 pair = {vq[0], vq[NPL - 1]};
                         __builtin_nontemporal_store(pair, (d2 *)dst);
                     } else if (live[0]) {
-                        __builtin_nontemporal_store(val[q][0], dst);
+                        __builtin_nontemporal_store(vq[0], dst);
                     }
                 }
                 continue;
@@ -226,32 +269,14 @@ __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__
             for (int q = 0; q <= J; ++q)
                 if (out.plane[q]) store_plane(out, q, idx, val[q][0]);
             if (ANG && out.plane[4]) store_plane(out, 4, idx, val[4][0]);
+            // the series' bf16 path keeps only the k-blocked copy (out.dir null)
+            if (DIR && out.dir) store_fmt(out.dir, out.dir_fmt, out.sub, idx, vdir[0]);
             if (KB) {
-                uint16_t hv[3];
-                split3(val[0][0], hv[0], hv[1], hv[2]);
                 const int g8 = eidx & ~7;
-                uint16_t *kb = (uint16_t *)out.kb + ((int64_t)(eidx >> 3) * out.kb_ld + p0) * 8;
-                if (g8 >= ch.emit_off && g8 + 8 <= e_end) {
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        uint32_t *w4 = kbw[KB ? q : 0];
-                        w4[0] = __builtin_amdgcn_alignbit(w4[1], w4[0], 16);
-                        w4[1] = __builtin_amdgcn_alignbit(w4[2], w4[1], 16);
-                        w4[2] = __builtin_amdgcn_alignbit(w4[3], w4[2], 16);
-                        w4[3] = (w4[3] >> 16) | ((uint32_t)hv[q] << 16);
-                    }
-                    if ((eidx & 7) == 7) {
-#pragma unroll
-                        for (int q = 0; q < 3; ++q) {
-                            const uint32_t *w4 = kbw[KB ? q : 0];
-                            const u4 vv = {w4[0], w4[1], w4[2], w4[3]};
-                            __builtin_nontemporal_store(vv, (u4 *)(kb + q * out.kb_sub));
-                        }
-                    }
-                } else {
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) __builtin_nontemporal_store(hv[q], kb + q * out.kb_sub + (eidx & 7));
-                }
+                const bool full = g8 >= ch.emit_off && g8 + 8 <= e_end;
+                const int64_t off = ((int64_t)(eidx >> 3) * out.kb_ld + p0) * 8;
+                if (out.kb) kb_push(kbw, val[0][0], (uint16_t *)out.kb + off, out.kb_sub, eidx, full);
+                if (DIR && out.kb_dir) kb_push(kbd, vdir[0], (uint16_t *)out.kb_dir + off, out.kb_sub, eidx, full);
             }
         }
     };
@@ -287,7 +312,7 @@ __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__
 // resident slot on 256 CUs, so the heaviest chains do not form a tail.
 constexpr int64_t kMinWorkgroups = 8192;
 
-template <int J, bool ANG, bool KB, int NPL>
+template <int J, bool ANG, bool KB, int NPL, bool DIR = false>
 hipError_t launch(const Plan &plan, const double *r, const double *th, int64_t P, const Planes &o, hipStream_t s)
 {
     const int64_t tiles = (P + (int64_t)kBlock * NPL - 1) / ((int64_t)kBlock * NPL);
@@ -295,19 +320,19 @@ hipError_t launch(const Plan &plan, const double *r, const double *th, int64_t P
     const Chain *list = use_pieces ? plan.d_pieces : plan.d_chains;
     const size_t count = use_pieces ? plan.pieces.size() : plan.chains.size();
     const dim3 grid((unsigned)tiles, (unsigned)count);
-    hipLaunchKernelGGL((chain_kernel<J, ANG, KB, NPL>), grid, dim3(kBlock), 0, s, list, plan.d_coefs, plan.d_emits,
+    hipLaunchKernelGGL((chain_kernel<J, ANG, KB, NPL, DIR>), grid, dim3(kBlock), 0, s, list, plan.d_coefs, plan.d_emits,
                        r, th, P, o);
     return hipGetLastError();
 }
 
-template <int J, bool ANG>
+template <int J, bool ANG, bool DIR = false>
 hipError_t launch_npl(const Plan &plan, const double *r, const double *th, int64_t P, const Planes &o, hipStream_t s)
 {
-    bool all_f64 = true;
+    bool all_f64 = !DIR || o.dir_fmt == F64;
     for (int q = 0; q < 5; ++q)
         if (o.plane[q] && o.fmt[q] != F64) all_f64 = false;
-    if (all_f64 && (o.ld % 2) == 0) return launch<J, ANG, false, 2>(plan, r, th, P, o, s);
-    return launch<J, ANG, false, 1>(plan, r, th, P, o, s);
+    if (all_f64 && (o.ld % 2) == 0) return launch<J, ANG, false, 2, DIR>(plan, r, th, P, o, s);
+    return launch<J, ANG, false, 1, DIR>(plan, r, th, P, o, s);
 }
 
 } // namespace
@@ -318,10 +343,17 @@ zp_status launch_chain_kernel(const Plan &plan, const double *d_r, const double 
     if (P <= 0 || plan.chains.empty()) return ZP_OK;
     if ((P + kBlock - 1) / kBlock > (int64_t)INT_MAX) return set_error(ZP_ERR_ARG, "too many points for one launch");
     hipError_t e;
-    if (out.kb) { // series forward: Z (+ dZ/dr for the cache) and the k-blocked copy
+    const bool dir = out.dir || out.kb_dir;
+    if (dir && (!angular || J != 1)) return set_error(ZP_ERR_ARG, "internal: directional output needs the basis, J = 1");
+    if (out.kb || out.kb_dir) { // series: k-blocked copies of Z and / or its directional derivative
         if (!angular || J > 1) return set_error(ZP_ERR_ARG, "internal: k-blocked output needs the basis, J <= 1");
-        e = J == 0 ? launch<0, true, true, 1>(plan, d_r, d_theta, P, out, s)
-                   : launch<1, true, true, 1>(plan, d_r, d_theta, P, out, s);
+        if (dir)
+            e = launch<1, true, true, 1, true>(plan, d_r, d_theta, P, out, s);
+        else
+            e = J == 0 ? launch<0, true, true, 1>(plan, d_r, d_theta, P, out, s)
+                       : launch<1, true, true, 1>(plan, d_r, d_theta, P, out, s);
+    } else if (dir) {
+        e = launch_npl<1, true, true>(plan, d_r, d_theta, P, out, s);
     } else if (angular) {
         switch (J) {
         case 0: e = launch_npl<0, true>(plan, d_r, d_theta, P, out, s); break;

@@ -511,6 +511,7 @@ __global__ __launch_bounds__(256) void convert_t_kernel(const double *__restrict
 __global__ __launch_bounds__(256) void convert_gather_t_kernel(const double *__restrict__ src,
                                                                const int32_t *__restrict__ perm, int64_t R, int64_t C,
                                                                int64_t lds, int ct, void *dst, int64_t ldd, int64_t sub)
+// (grid.x covers the dst columns written, grid.y the dst rows)
 {
     __shared__ double tile[32][33];
     const int64_t r0 = (int64_t)blockIdx.x * 32; // chain-major rows = dst columns
@@ -625,9 +626,10 @@ zp_status launch_convert(const double *src, int64_t R, int64_t C, int64_t lds, i
 }
 
 zp_status launch_convert_gather_t(const double *src, const int32_t *perm, int64_t R, int64_t C, int64_t lds,
-                                  int ct, void *dst, int64_t ldd, int64_t rows_pad, int64_t sub, hipStream_t s)
+                                  int ct, void *dst, int64_t ldd, int64_t rows_pad, int64_t sub, int64_t ncols,
+                                  hipStream_t s)
 {
-    const dim3 grid((unsigned)(ldd / 32), (unsigned)(rows_pad / 32));
+    const dim3 grid((unsigned)(ncols / 32), (unsigned)(rows_pad / 32));
     hipLaunchKernelGGL(convert_gather_t_kernel, grid, dim3(256), 0, s, src, perm, R, C, lds, ct, dst, ldd, sub);
     return hip_check(hipGetLastError(), "convert launch");
 }

@@ -115,8 +115,71 @@ std::shared_ptr<Plan> build_plan_host(const int32_t *n, const int32_t *m, int64_
     return plan;
 }
 
+// c_s = (-1)^s C(n-s, s) C(n-2s, (n-m)/2 - s) (Eq. radial-part-eq-binom), in
+// 64-bit-significand arithmetic, times (n-2s)!/(n-2s-j)!.
+static double direct_coef(int n, int m, int s, int j)
+{
+    const int e = n - 2 * s;
+    if (e < j) return 0.0;
+    auto binom = [](int top, int k) {
+        long double v = 1.0L;
+        for (int i = 1; i <= k; ++i) v = v * (long double)(top - k + i) / (long double)i;
+        return v;
+    };
+    long double c = binom(n - s, s) * binom(n - 2 * s, (n - m) / 2 - s);
+    for (int t = 0; t < j; ++t) c *= (long double)(e - t);
+    return (double)((s & 1) ? -c : c);
+}
+
+zp_status get_direct_table(Plan &plan)
+{
+    std::call_once(plan.direct_once, [&plan] {
+        const size_t M = plan.n.size();
+        std::vector<int64_t> off(M + 1, 0);
+        for (size_t i = 0; i < M; ++i) {
+            const int K = (plan.n[i] - std::abs(plan.m[i])) / 2;
+            off[i + 1] = off[i] + 4 * (K + 1);
+        }
+        std::vector<double> coef((size_t)off[M]);
+        for (size_t i = 0; i < M; ++i) {
+            const int n = plan.n[i], m = std::abs(plan.m[i]), K = (n - m) / 2;
+            for (int j = 0; j < 4; ++j)
+                for (int s = 0; s <= K; ++s) coef[(size_t)off[i] + (size_t)j * (K + 1) + s] = direct_coef(n, m, s, j);
+        }
+        // layout: offsets int64[M+1] | n int32[M] | m int32[M] | coefficients
+        const size_t a = (M + 1) * sizeof(int64_t), a_al = (a + 255) / 256 * 256;
+        const size_t b = M * sizeof(int32_t), b_al = (b + 255) / 256 * 256;
+        const size_t total = a_al + 2 * b_al + coef.size() * sizeof(double);
+        std::vector<unsigned char> host(total, 0);
+        std::copy_n((const unsigned char *)off.data(), a, host.data());
+        std::copy_n((const unsigned char *)plan.n.data(), b, host.data() + a_al);
+        std::copy_n((const unsigned char *)plan.m.data(), b, host.data() + a_al + b_al);
+        std::copy_n((const unsigned char *)coef.data(), coef.size() * sizeof(double), host.data() + a_al + 2 * b_al);
+        void *d = nullptr;
+        zp_status st = hip_check(hipMalloc(&d, total), "hipMalloc(direct table)");
+        if (st == ZP_OK) st = hip_check(hipMemcpy(d, host.data(), total, hipMemcpyHostToDevice), "hipMemcpy(direct table)");
+        plan.direct_status = st;
+        if (st == ZP_OK) {
+            plan.d_direct = d;
+            plan.d_direct_off = (const int64_t *)d;
+            plan.d_direct_n = (const int32_t *)((unsigned char *)d + a_al);
+            plan.d_direct_m = (const int32_t *)((unsigned char *)d + a_al + b_al);
+            plan.d_direct_coef = (const double *)((unsigned char *)d + a_al + 2 * b_al);
+        }
+    });
+    return plan.direct_status == ZP_OK ? ZP_OK : set_error(plan.direct_status, "direct table upload failed");
+}
+
 Plan::~Plan()
 {
+    if (d_direct) {
+        int cur = -1;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(device);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(d_direct);
+        if (cur >= 0) (void)hipSetDevice(cur);
+    }
     if (dmem) {
         int cur = -1;
         (void)hipGetDevice(&cur);

@@ -115,6 +115,36 @@ struct WsLayout {
     }
 };
 
+// Workspace of the forward-mode derivative for one chunk: the stacked
+// coefficients [nblk * Mp][Bp] (transposed for bf16) and the stacked basis
+// [nblk * Mp][Pcp] (k-blocked for bf16), nblk = 2 (Z with the coefficient
+// tangent, and the directional derivative of Z with c).
+struct JvpLayout {
+    size_t c_off, z_off, total;
+    JvpLayout(int64_t M, int64_t Pc, int64_t B, int ct)
+    {
+        const int64_t K2 = 2 * pad_up(M);
+        const size_t e = ct_bytes(ct);
+        c_off = 0;
+        z_off = al(e * (size_t)K2 * (size_t)pad_up(B));
+        total = z_off + al(e * (size_t)K2 * (size_t)pad_up(Pc));
+    }
+};
+
+int64_t jvp_chunk_for(int64_t M, int64_t P, int64_t B, int ct, size_t ws_bytes)
+{
+    if (JvpLayout(M, P, B, ct).total <= ws_bytes) return P;
+    int64_t lo = 0, hi = pad_up(P) / kPad;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (JvpLayout(M, mid * kPad, B, ct).total <= ws_bytes)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return std::min<int64_t>(lo * kPad, P);
+}
+
 // Largest chunk (multiple of kPad, <= P) whose workspace fits ws_bytes; 0 if none.
 int64_t chunk_for(int64_t M, int64_t P, int64_t B, int ct, bool fwd, bool bwd, bool have_cache, size_t ws_bytes)
 {
@@ -176,9 +206,12 @@ zp_status zp_series_workspace(int64_t M, int64_t P, int64_t B, int32_t prec, siz
     if (!full_bytes || M < 0 || P < 0 || B < 0) return set_error(ZP_ERR_ARG, "bad argument");
     if (prec < ZP_FP64 || prec > ZP_BF16X3) return set_error(ZP_ERR_PREC, "unknown prec");
     const int ct = ct_of(prec);
-    // Sized for the most demanding use: backward without a cache.
-    *full_bytes = std::max(WsLayout(M, P, B, ct, true, true, false).total, (size_t)256);
-    if (min_bytes) *min_bytes = std::max(WsLayout(M, std::min<int64_t>(P, kPad), B, ct, true, true, false).total, (size_t)256);
+    // Sized for the most demanding use: backward without a cache, or the
+    // forward-mode derivative.
+    const int64_t P1 = std::min<int64_t>(P, kPad);
+    *full_bytes = std::max({WsLayout(M, P, B, ct, true, true, false).total, JvpLayout(M, P, B, ct).total, (size_t)256});
+    if (min_bytes)
+        *min_bytes = std::max({WsLayout(M, P1, B, ct, true, true, false).total, JvpLayout(M, P1, B, ct).total, (size_t)256});
     return ZP_OK;
 }
 
@@ -206,7 +239,7 @@ zp_status zp_series_fwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
     const int64_t Mp = L.Mp, Bp = L.Bp;
     void *cbuf = ws + L.c_off;
     if (ct == CT_BF3) // B(k = e, j = b) = c[perm[e]][b], k-contiguous
-        st = launch_convert_gather_t(d_c, plan->d_perm, M, B, B, ct, cbuf, Mp, Bp, Bp * Mp, s);
+        st = launch_convert_gather_t(d_c, plan->d_perm, M, B, B, ct, cbuf, Mp, Bp, Bp * Mp, Mp, s);
     else // B(k = q, j = b) = c[q][b]
         st = launch_convert(d_c, M, B, B, ct, cbuf, Bp, Mp, Mp * Bp, false, s);
     if (st != ZP_OK) return st;
@@ -387,3 +420,106 @@ zp_status zp_series_bwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
 }
 
 } // extern "C"
+
+extern "C" zp_status zp_series_jvp(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r,
+                                   const double *d_theta, int64_t P, const double *d_c, int64_t B, int32_t prec,
+                                   const double *d_tc, const double *d_tr, const double *d_ttheta, double *d_tf,
+                                   void *d_ws, size_t ws_bytes, void *stream)
+{
+    zp_status st = common_checks(h_n, h_m, M, P, B, prec);
+    if (st != ZP_OK) return st;
+    if (P == 0 || B == 0) return ZP_OK;
+    if (!d_tf || !d_r || !d_theta) return set_error(ZP_ERR_ARG, "null pointer");
+    const bool with_c = d_tc != nullptr;                     // Z^T tc
+    const bool with_dir = d_tr != nullptr || d_ttheta != nullptr; // (dr dZ/dr + dtheta dZ/dtheta)^T c
+    if (with_dir && !d_c) return set_error(ZP_ERR_ARG, "null coefficients with a point tangent");
+    hipStream_t s = (hipStream_t)stream;
+    if (M == 0 || (!with_c && !with_dir)) // the tangent is zero
+        return launch_zero_pad(d_tf, CT_F64, 0, 0, P, B, 0, s);
+    if (!d_ws || ((uintptr_t)d_ws & 255)) return set_error(ZP_ERR_ARG, "workspace must be non-null and 256-byte aligned");
+    const int ct = ct_of(prec);
+    const int64_t Pc = jvp_chunk_for(M, P, B, ct, ws_bytes);
+    if (Pc <= 0) return set_error(ZP_ERR_WORKSPACE, "workspace smaller than the minimum (zp_series_workspace)");
+    std::shared_ptr<Plan> plan;
+    st = get_plan(h_n, h_m, M, &plan);
+    if (st != ZP_OK) return st;
+
+    const int64_t Mp = pad_up(M), Bp = pad_up(B);
+    const int nblk = (with_c ? 1 : 0) + (with_dir ? 1 : 0);
+    const int64_t K = nblk * Mp;
+    const size_t esz = ct == CT_BF3 ? 2 : ct_bytes(ct); // per plane element
+    const JvpLayout L(M, Pc, B, ct);
+    char *ws = (char *)d_ws;
+    char *cbuf = ws + L.c_off;
+    // stacked coefficients: block 0 = tc (if any), then c (if a point tangent)
+    int blk = 0;
+    for (int which = 0; which < 2; ++which) {
+        const double *src = which == 0 ? (with_c ? d_tc : nullptr) : (with_dir ? d_c : nullptr);
+        if (!src) continue;
+        if (ct == CT_BF3) // [Bp][K], k contiguous, chain-major order
+            st = launch_convert_gather_t(src, plan->d_perm, M, B, B, ct, cbuf + esz * (size_t)(blk * Mp), K, Bp,
+                                         Bp * K, Mp, s);
+        else // [K][Bp]
+            st = launch_convert(src, M, B, B, ct, cbuf + esz * (size_t)(blk * Mp) * (size_t)Bp, Bp, Mp, 0, false, s);
+        if (st != ZP_OK) return st;
+        ++blk;
+    }
+    for (int64_t p0 = 0; p0 < P; p0 += Pc) {
+        const int64_t pc = std::min(Pc, P - p0);
+        const int64_t pcp = pad_up(pc);
+        char *zbuf = ws + L.z_off;
+        Planes o{};
+        o.ld = pcp;
+        const int zfmt = ct == CT_F64 ? F64 : F32;
+        if (ct == CT_BF3) {
+            o.kb_ld = pcp;
+            o.kb_sub = K * pcp;
+            for (int b2 = 0; b2 < nblk; ++b2) {
+                st = launch_zero_kb8(zbuf + esz * (size_t)(b2 * Mp) * (size_t)pcp, M, Mp, pc, pcp, K * pcp, s);
+                if (st != ZP_OK) return st;
+            }
+            if (with_c) o.kb = zbuf;
+            if (with_dir) o.kb_dir = zbuf + esz * (size_t)((with_c ? 1 : 0) * Mp) * (size_t)pcp;
+        } else {
+            o.sub = K * pcp;
+            for (int b2 = 0; b2 < nblk; ++b2) {
+                st = launch_zero_pad(zbuf + esz * (size_t)(b2 * Mp) * (size_t)pcp, ct, M, pc, Mp, pcp, 0, s);
+                if (st != ZP_OK) return st;
+            }
+            if (with_c) {
+                o.plane[0] = zbuf;
+                o.fmt[0] = zfmt;
+            }
+            if (with_dir) {
+                o.dir = zbuf + esz * (size_t)((with_c ? 1 : 0) * Mp) * (size_t)pcp;
+                o.dir_fmt = zfmt;
+            }
+        }
+        if (with_dir) {
+            o.dir_r = d_tr ? d_tr + p0 : nullptr;
+            o.dir_th = d_ttheta ? d_ttheta + p0 : nullptr;
+        }
+        st = launch_chain_kernel(*plan, d_r + p0, d_theta + p0, pc, with_dir ? 1 : 0, true, o, s);
+        if (st != ZP_OK) return st;
+
+        GemmDesc g{};
+        g.ct = ct;
+        if (ct == CT_BF3) {
+            g.a = Operand{zbuf, pcp, K * pcp, LAY_KB8};
+            g.b = Operand{cbuf, K, Bp * K, LAY_KC};
+        } else {
+            g.a = Operand{zbuf, pcp, K * pcp, LAY_XC};
+            g.b = Operand{cbuf, Bp, K * Bp, LAY_XC};
+        }
+        g.M = pc;
+        g.N = B;
+        g.K = K;
+        g.splits = 1;
+        g.epi = EPI_STORE;
+        g.C = d_tf + p0 * B;
+        g.ldc = B;
+        st = launch_gemm(g, s);
+        if (st != ZP_OK) return st;
+    }
+    return ZP_OK;
+}

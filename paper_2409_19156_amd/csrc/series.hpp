@@ -63,9 +63,11 @@ zp_status launch_gemm(const GemmDesc &g, hipStream_t s);
 zp_status launch_convert(const double *src, int64_t R, int64_t C, int64_t lds, int ct, void *dst, int64_t ldd,
                          int64_t rows_pad, int64_t sub, bool transpose, hipStream_t s);
 
-// dst[c][e] = src[perm[e]][c] (e < R, zero padded), dst [rows_pad][ldd].
+// dst[c][e] = src[perm[e]][c] (e < R, zero padded) for columns e < ncols of
+// dst [rows_pad][ldd] (ncols a multiple of 32, <= ldd).
 zp_status launch_convert_gather_t(const double *src, const int32_t *perm, int64_t R, int64_t C, int64_t lds,
-                                  int ct, void *dst, int64_t ldd, int64_t rows_pad, int64_t sub, hipStream_t s);
+                                  int ct, void *dst, int64_t ldd, int64_t rows_pad, int64_t sub, int64_t ncols,
+                                  hipStream_t s);
 
 // Zero the pad (modes >= M, points >= P) of a k-blocked bf16 operand.
 zp_status launch_zero_kb8(void *dst, int64_t M, int64_t Mp, int64_t P, int64_t ld, int64_t sub, hipStream_t s);

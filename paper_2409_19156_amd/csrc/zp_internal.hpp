@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -79,8 +80,23 @@ struct Plan {
     const Coef *d_coefs = nullptr;
     const Emit *d_emits = nullptr;
     const int32_t *d_perm = nullptr; // d_perm[e] = emits[e].col: chain-major order -> column
+    // Coefficient table of the direct (closed-form) evaluation, built on first
+    // use: per mode, for j = 0..3, the K+1 values c_s (n-2s)!/(n-2s-j)! of
+    // d^j/dr^j of Eq. (radial-part-eq), rounded to double.
+    std::once_flag direct_once;
+    zp_status direct_status = ZP_OK;
+    void *d_direct = nullptr;
+    const int64_t *d_direct_off = nullptr; // per mode: offset of its 4 (K+1) coefficients
+    const int32_t *d_direct_n = nullptr, *d_direct_m = nullptr;
+    const double *d_direct_coef = nullptr;
     ~Plan();
 };
+
+// Device table for zp_radial_direct (uploaded once per plan).
+zp_status get_direct_table(Plan &plan);
+
+// Direct evaluation of the closed form: out[j][i][p] for j <= J.
+zp_status launch_direct_kernel(const Plan &plan, const double *d_r, int64_t P, int J, double *out, hipStream_t s);
 
 // Validates the modes; returns ZP_OK or ZP_ERR_MODE (with the offending index
 // in *bad).
@@ -105,6 +121,11 @@ enum PlaneFmt : int32_t { F64 = 0, F32 = 1, B16X3 = 2 };
 // the k-blocked layout the series forward contracts over: the mode index is
 // the emission index e (chain-major order, see Plan::d_perm) and element
 // (e, p) sits at ((e/8)*kb_ld + p)*8 + e%8.
+// dir, if not null, receives the directional derivative
+//   dZ = dr[p] dZ/dr + dtheta[p] dZ/dtheta
+// of the basis along per-point tangents (dr, dtheta; either may be null),
+// in format dir_fmt with the planes' ld and sub; kb_dir, if not null, gets its
+// k-blocked bf16 copy (like kb).
 struct Planes {
     void *plane[5];
     int64_t ld;
@@ -113,6 +134,11 @@ struct Planes {
     void *kb;
     int64_t kb_ld;
     int64_t kb_sub;
+    void *dir;
+    int32_t dir_fmt;
+    const double *dir_r;
+    const double *dir_th;
+    void *kb_dir;
 };
 
 // Launch the chain kernel: radial only (angular = false) or basis.  J is the

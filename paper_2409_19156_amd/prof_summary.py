@@ -1,21 +1,37 @@
-"""Summarise a rocprofv3 kernel-trace database (rocpd SQLite) as a text table.
+"""Summarise a rocprofv3 kernel trace as a text table.
 
-    python -m paper_2409_19156_amd.prof_summary <run_results.db> [command ...]
+    python -m paper_2409_19156_amd.prof_summary <run_results.db | run_kernel_stats.csv>
 
-Prints per-kernel call count, total, average, min and max duration (us) and
-share of GPU time, most expensive first.
+Accepts the rocpd SQLite database or the ``--stats --output-format csv``
+kernel statistics file.  Prints per-kernel call count, total, average, min and
+max duration (us) and share of GPU time, most expensive first.
 """
 from __future__ import annotations
 
+import csv
 import sqlite3
 import sys
 
 
-def summarise(db_path: str, limit: int = 30) -> str:
-    con = sqlite3.connect(db_path)
-    rows = con.execute(
+def _rows_db(path):
+    con = sqlite3.connect(path)
+    return con.execute(
         "select name, count(*), sum(duration), avg(duration), min(duration), max(duration) "
         "from kernels group by name order by sum(duration) desc").fetchall()
+
+
+def _rows_csv(path):
+    rows = []
+    with open(path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            rows.append((r["Name"], int(r["Calls"]), float(r["TotalDurationNs"]), float(r["AverageNs"]),
+                         float(r["MinNs"]), float(r["MaxNs"])))
+    rows.sort(key=lambda x: -x[2])
+    return rows
+
+
+def summarise(path: str, limit: int = 30) -> str:
+    rows = _rows_csv(path) if path.endswith(".csv") else _rows_db(path)
     total = sum(r[2] for r in rows) or 1
     out = ["| kernel | calls | total us | avg us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
     for name, n, tot, avg, mn, mx in rows[:limit]:

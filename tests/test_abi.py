@@ -56,11 +56,14 @@ def test_invalid_modes(lib, n, m):
     n, m = _modes(n, m)
     assert lib.zp_radial(n.ctypes.data, m.ctypes.data, n.size, FAKE, 4, 0, FAKE, None) == ERR_MODE
     assert b"violates" in lib.zp_last_error()
+    assert lib.zp_radial_direct(n.ctypes.data, m.ctypes.data, n.size, FAKE, 4, 0, FAKE, None) == ERR_MODE
     assert lib.zp_basis(n.ctypes.data, m.ctypes.data, n.size, FAKE, FAKE, 4, 1, FAKE, None) == ERR_MODE
     assert lib.zp_series_fwd(n.ctypes.data, m.ctypes.data, n.size, FAKE, FAKE, 4, FAKE, 2, 0, FAKE, None, FAKE,
                              1 << 20, None) == ERR_MODE
     assert lib.zp_series_bwd(n.ctypes.data, m.ctypes.data, n.size, FAKE, FAKE, 4, FAKE, 2, 0, FAKE, None, FAKE,
                              FAKE, FAKE, FAKE, 1 << 20, None) == ERR_MODE
+    assert lib.zp_series_jvp(n.ctypes.data, m.ctypes.data, n.size, FAKE, FAKE, 4, FAKE, 2, 0, FAKE, FAKE, FAKE,
+                             FAKE, FAKE, 1 << 20, None) == ERR_MODE
 
 
 def test_order_mask_prec_and_sizes(lib):
@@ -68,6 +71,7 @@ def test_order_mask_prec_and_sizes(lib):
     nd, md = n.ctypes.data, m.ctypes.data
     for bad in (-1, 4, 7):
         assert lib.zp_radial(nd, md, 2, FAKE, 4, bad, FAKE, None) == ERR_ORDER
+        assert lib.zp_radial_direct(nd, md, 2, FAKE, 4, bad, FAKE, None) == ERR_ORDER
     for mask in (0, 32, 33):
         assert lib.zp_basis(nd, md, 2, FAKE, FAKE, 4, mask, FAKE, None) == ERR_ARG
     assert lib.zp_radial(nd, md, -1, FAKE, 4, 0, FAKE, None) == ERR_ARG
@@ -86,6 +90,15 @@ def test_order_mask_prec_and_sizes(lib):
                              None) == ERR_ARG
     assert lib.zp_series_fwd(nd, md, 2, FAKE, FAKE, 4, FAKE, 2, 0, FAKE, None, FAKE, 16, None) == ERR_WS
     assert lib.zp_series_bwd(nd, md, 2, FAKE, FAKE, 4, FAKE, 2, 0, FAKE, None, FAKE, FAKE, FAKE, FAKE, 16,
+                             None) == ERR_WS
+    # forward mode: bad precision, null output, point tangent without c, small workspace
+    assert lib.zp_series_jvp(nd, md, 2, FAKE, FAKE, 4, FAKE, 2, 5, FAKE, None, None, FAKE, FAKE, 1 << 20,
+                             None) == ERR_PREC
+    assert lib.zp_series_jvp(nd, md, 2, FAKE, FAKE, 4, FAKE, 2, 0, FAKE, None, None, None, FAKE, 1 << 20,
+                             None) == ERR_ARG
+    assert lib.zp_series_jvp(nd, md, 2, FAKE, FAKE, 4, None, 2, 0, None, FAKE, None, FAKE, FAKE, 1 << 20,
+                             None) == ERR_ARG
+    assert lib.zp_series_jvp(nd, md, 2, FAKE, FAKE, 4, FAKE, 2, 0, FAKE, None, None, FAKE, FAKE, 16,
                              None) == ERR_WS
 
 

@@ -1,0 +1,66 @@
+"""Accuracy maps of the paper's accuracy study (Sec. 4, first figure): every
+radial pair with 0 <= m <= n <= 50 at 100 linearly spaced r in [0, 1], orders
+0..3, per-mode error = max over points of |computed - exact|, for the Jacobi
+recurrence (zp_radial) and for direct FP64 evaluation of the closed form
+(zp_radial_direct), both against the quad-precision oracle.
+
+The paper's qualitative findings, checked here: the recurrence stays accurate
+(its stated maximum for n <= 50 is 2.05e-14), direct evaluation degrades with
+n - m, is most accurate along n = m, and is worst in the corner of highest n
+and lowest m, with errors above 1.  The paper names (50, 0) as the worst mode
+of its implementation; which mode of that corner comes out on top depends on
+the rounding of the alternating sum (the six worst modes, all with n >= 49 and
+m <= 6, lie within a factor of a few of each other), so the test requires the
+worst mode to be in that corner and (50, 0) to be within a factor 10 of it.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import zp_workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def maps(oracle_mod):
+    import paper_2409_19156_amd as zp
+
+    n, m = W.radial_pairs(50)
+    r = np.linspace(0.0, 1.0, 100)
+    rd = torch.from_numpy(r).cuda()
+    ref = oracle_mod.radial(n, m, r, 3)
+    rec = zp.radial(n, m, rd, 3).cpu().numpy()
+    direct = zp.radial_direct(n, m, rd, 3).cpu().numpy()
+    e_rec = np.abs(rec - ref).max(axis=2)      # [4, modes]
+    e_dir = np.abs(direct - ref).max(axis=2)
+    for j in range(4):
+        print(f"order {j}: recurrence max {e_rec[j].max():.3g} mean {e_rec[j].mean():.3g} | "
+              f"direct max {e_dir[j].max():.3g} mean {e_dir[j].mean():.3g}", flush=True)
+    sys.stdout.flush()
+    return n, m, e_rec, e_dir
+
+
+def test_recurrence_within_papers_stated_error(maps):
+    n, m, e_rec, _ = maps
+    assert e_rec[0].max() <= 2.05e-14
+    for j in range(4):
+        assert np.all(e_rec[j] <= 1e-13 * (n + 1.0) ** (2 * j))
+
+
+def test_direct_evaluation_degrades_as_the_paper_reports(maps):
+    n, m, e_rec, e_dir = maps
+    k = int(np.argmax(e_dir[0]))
+    assert n[k] >= 49 and m[k] <= 6, (n[k], m[k])
+    k50 = int(np.flatnonzero((n == 50) & (m == 0))[0])
+    assert e_dir[0][k50] >= e_dir[0].max() / 10
+    assert e_dir[0].max() > 1e-3
+    diag = n == m
+    assert e_dir[0][diag].max() <= 1e-13
+    # orders of magnitude worse than the recurrence at high n - m
+    hi = (n - m) >= 40
+    assert e_dir[0][hi].min() > 100 * e_rec[0][hi].max()

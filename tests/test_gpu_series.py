@@ -216,3 +216,92 @@ def test_bad_arguments_raise(zp):
     ws = torch.empty(64, dtype=torch.uint8, device="cuda")
     with pytest.raises(zp.ZpError):
         zp.series_forward(n, m, r, r, c, "fp64", ws=ws)
+
+
+# ------------------------------------------------------- forward mode (JVP) --
+
+def _jvp_case(seed=5, nmax=40, P=3000, B=24):
+    rng = np.random.default_rng(seed)
+    n, m = W.ansi_modes(nmax)
+    r, th = np.sqrt(rng.random(P)), 2 * np.pi * rng.random(P)
+    c = rng.standard_normal((n.size, B)) / (n + 1.0)[:, None]
+    tc = rng.standard_normal((n.size, B))
+    tr, tt = rng.standard_normal(P), rng.standard_normal(P)
+    return n, m, r, th, c, tc, tr, tt
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_jvp_matches_oracle(zp, oracle_mod, prec):
+    """tf = Z^T tc + (tr dZ/dr + ttheta dZ/dtheta)^T c against the oracle basis."""
+    n, m, r, th, c, tc, tr, tt = _jvp_case()
+    Z, Zr, Zt = oracle_mod.series_basis(n, m, r, th)
+    ref = Z.T @ tc + tr[:, None] * (Zr.T @ c) + tt[:, None] * (Zt.T @ c)
+    got = zp.series_jvp(n, m, _dev(r), _dev(th), _dev(c), _dev(tc), _dev(tr), _dev(tt), prec).cpu().numpy()
+    e = _rel(got, ref)
+    _say(f"  jvp {prec}: rel err {e:.3g}")
+    assert e <= TOL[prec]
+
+
+def test_jvp_partial_tangents(zp, oracle_mod):
+    n, m, r, th, c, tc, tr, tt = _jvp_case(seed=6, nmax=20, P=700, B=5)
+    Z, Zr, Zt = oracle_mod.series_basis(n, m, r, th)
+    d = {k: _dev(v) for k, v in dict(r=r, th=th, c=c, tc=tc, tr=tr, tt=tt).items()}
+    cases = [
+        (dict(tc=d["tc"]), Z.T @ tc),
+        (dict(tr=d["tr"]), tr[:, None] * (Zr.T @ c)),
+        (dict(ttheta=d["tt"]), tt[:, None] * (Zt.T @ c)),
+        (dict(tc=d["tc"], ttheta=d["tt"]), Z.T @ tc + tt[:, None] * (Zt.T @ c)),
+    ]
+    for prec in ("fp64", "bf16x3"):
+        for kw, ref in cases:
+            got = zp.series_jvp(n, m, d["r"], d["th"], d["c"], prec=prec, **kw).cpu().numpy()
+            assert _rel(got, ref) <= TOL[prec], (prec, list(kw))
+    zero = zp.series_jvp(n, m, d["r"], d["th"], d["c"]).cpu().numpy()
+    assert np.all(zero == 0)
+
+
+def test_jvp_vjp_duality(zp):
+    """<g, J v> = <J^T g, v> between the forward-mode and reverse-mode kernels."""
+    n, m, r, th, c, tc, tr, tt = _jvp_case(seed=7, nmax=30, P=2000, B=16)
+    g = np.random.default_rng(8).standard_normal((r.size, c.shape[1]))
+    tf = zp.series_jvp(n, m, _dev(r), _dev(th), _dev(c), _dev(tc), _dev(tr), _dev(tt)).cpu().numpy()
+    gc, gr, gt = (x.cpu().numpy() for x in zp.series_backward(n, m, _dev(r), _dev(th), _dev(c), _dev(g)))
+    lhs = np.sum(g * tf)
+    rhs = np.sum(gc * tc) + np.sum(gr * tr) + np.sum(gt * tt)
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + abs(rhs))
+
+
+def test_forward_mode_autograd(zp):
+    """torch forward-mode AD through ZernikeSeries, and gradcheck of both modes."""
+    import torch.autograd.forward_ad as fwAD
+
+    n, m, r, th, c, tc, tr, tt = _jvp_case(seed=9, nmax=12, P=50, B=3)
+    with fwAD.dual_level():
+        f = zp.series(fwAD.make_dual(_dev(c), _dev(tc)), fwAD.make_dual(_dev(r), _dev(tr)),
+                      fwAD.make_dual(_dev(th), _dev(tt)), n, m)
+        tangent = fwAD.unpack_dual(f).tangent
+    ref = zp.series_jvp(n, m, _dev(r), _dev(th), _dev(c), _dev(tc), _dev(tr), _dev(tt))
+    assert torch.equal(tangent, ref)
+    n2, m2 = W.ansi_modes(5)
+    rng = np.random.default_rng(10)
+    rr = _dev(0.1 + 0.8 * rng.random(6)).requires_grad_()
+    tt2 = _dev(2 * np.pi * rng.random(6)).requires_grad_()
+    cc = _dev(rng.standard_normal((n2.size, 2))).requires_grad_()
+    assert torch.autograd.gradcheck(lambda c_, r_, t_: zp.series(c_, r_, t_, n2, m2), (cc, rr, tt2), eps=1e-6,
+                                    atol=1e-8, rtol=1e-6, check_forward_ad=True)
+
+
+def test_jvp_n64_full_size_sampled(zp, n64_ref, oracle_mod):
+    """The n <= 64 workload's forward-mode derivative, sampled rows, per precision."""
+    wl, ps, _, _ = n64_ref
+    rng = np.random.default_rng(77)
+    tc = rng.standard_normal(wl.c.shape) / (wl.n + 1.0)[:, None]
+    tr, tt = rng.standard_normal(wl.P), rng.standard_normal(wl.P)
+    Zs, Zrs, Zts = oracle_mod.series_basis(wl.n, wl.m, wl.r[ps], wl.theta[ps])
+    ref = Zs.T @ tc + tr[ps, None] * (Zrs.T @ wl.c) + tt[ps, None] * (Zts.T @ wl.c)
+    for prec in ("bf16x3", "fp32", "fp64"):
+        got = zp.series_jvp(wl.n, wl.m, _dev(wl.r), _dev(wl.theta), _dev(wl.c), _dev(tc), _dev(tr), _dev(tt),
+                            prec).cpu().numpy()[ps]
+        e = _rel(got, ref)
+        _say(f"  jvp n64 {prec}: rel err {e:.3g} (sampled)")
+        assert e <= TOL[prec]
