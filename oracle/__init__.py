@@ -13,6 +13,10 @@ does, and this package imports nothing from it.
 * ``series_*`` -- the Zernike series f = sum_k c_k Z_k (Eq. zernike-poly
   summed over modes) and its exact adjoint, as plain float64 matrix products
   on the oracle basis rounded to double.
+* ``fourier`` / ``series3d_*`` -- the three-dimensional spectral series of the
+  paper's duplicated-mode use (Sec. 3, footnote): modes (n, m, l), value
+  sum_j c_j R_n^m(r) F_m(theta) F_l(phi) with F the Fourier basis, evaluated
+  over the full (duplicated) mode list with no deduplication, and its adjoint.
 """
 from __future__ import annotations
 
@@ -170,3 +174,37 @@ def series_bwd(Z, Zr, Zt, c, g):
     grad_r = np.einsum("pb,pb->p", g, Zr.T @ c)
     grad_t = np.einsum("pb,pb->p", g, Zt.T @ c)
     return grad_c, grad_r, grad_t
+
+
+def fourier(l, phi, deriv: int = 0):
+    """Fourier factor F_l(phi) = cos(l phi) for l >= 0 and sin(|l| phi) for
+    l < 0 (the convention of Eq. zernike-poly for the angle), or its first
+    phi-derivative.  The product l*phi and the trigonometric functions are
+    taken in long double; returns float64 [len(l), len(phi)]."""
+    l = np.asarray(l, dtype=np.int64).reshape(-1, 1)
+    ph = np.asarray(phi, dtype=np.float64).reshape(1, -1)
+    a = np.abs(l).astype(np.longdouble)
+    arg = a * ph.astype(np.longdouble)
+    cs, sn = np.cos(arg), np.sin(arg)
+    if deriv == 0:
+        out = np.where(l >= 0, cs, sn)
+    else:  # d/dphi cos(a phi) = -a sin(a phi); d/dphi sin(a phi) = a cos(a phi)
+        out = np.where(l >= 0, -a * sn, a * cs)
+    return out.astype(np.float64)
+
+
+def series3d_fwd(Z, F, c):
+    """f[p, q, b] = sum_j Z[j, p] F[j, q] c[j, b]: Z is the basis of the full
+    mode list [J, P], F the Fourier factors [J, Q], c [J, B]."""
+    return np.einsum("jp,jq,jb->pqb", np.asarray(Z), np.asarray(F), np.asarray(c), optimize=True)
+
+
+def series3d_bwd(Z, Zr, Zt, F, dF, c, g):
+    """Adjoint of ``series3d_fwd`` for an upstream gradient g [P, Q, B], with
+    respect to c, r, theta and phi (dF = dF/dphi)."""
+    Z, Zr, Zt, F, dF, c, g = (np.asarray(a) for a in (Z, Zr, Zt, F, dF, c, g))
+    grad_c = np.einsum("jp,jq,pqb->jb", Z, F, g, optimize=True)
+    grad_r = np.einsum("pqb,jp,jq,jb->p", g, Zr, F, c, optimize=True)
+    grad_t = np.einsum("pqb,jp,jq,jb->p", g, Zt, F, c, optimize=True)
+    grad_phi = np.einsum("pqb,jp,jq,jb->q", g, Z, dF, c, optimize=True)
+    return grad_c, grad_r, grad_t, grad_phi

@@ -153,3 +153,53 @@ __all__ = [
     "radial_pairs", "ansi_modes", "cgl_polar_grid", "clustered_r", "disc_points", "Workload",
     "radial_n16", "basis_L50", "radial_n200", "series_n40", "series_n64", "n_entries",
 ]
+
+
+@dataclass
+class Spectral3D:
+    """Three-dimensional spectral series: modes (n, m, l), polar points
+    (r_p, theta_p) times toroidal angles phi_q, B coefficient sets."""
+    name: str
+    n: np.ndarray
+    m: np.ndarray
+    l: np.ndarray
+    r: np.ndarray
+    theta: np.ndarray
+    phi: np.ndarray
+    c: np.ndarray
+    g: np.ndarray
+
+    @property
+    def J(self) -> int:
+        return int(self.n.size)
+
+
+def spectral3d_modes(nmax: int, lmax: int):
+    """Every ANSI Zernike mode n <= nmax paired with every l in [-lmax, lmax]
+    (l outer), so each (n, m) appears 2 lmax + 1 times."""
+    n2, m2 = ansi_modes(nmax)
+    L = np.arange(-lmax, lmax + 1)
+    return np.tile(n2, L.size), np.tile(m2, L.size), np.repeat(L, n2.size).astype(np.int32)
+
+
+def spectral3d(name: str, nmax: int, lmax: int, r, theta, nphi: int, nb: int, seed: int) -> Spectral3D:
+    rng = np.random.default_rng(seed)
+    n, m, l = spectral3d_modes(nmax, lmax)
+    phi = 2.0 * np.pi * np.arange(nphi, dtype=np.float64) / nphi
+    scale = 1.0 / ((n + 1.0) * (np.abs(l) + 1.0))
+    c = rng.standard_normal((n.size, nb)) * scale[:, None]
+    g = rng.standard_normal((np.asarray(r).size, nphi, nb))
+    return Spectral3D(name, n, m, l, np.asarray(r), np.asarray(theta), phi, c, g)
+
+
+def spectral3d_small(seed: int = 5) -> Spectral3D:
+    """n <= 8 (45 modes) x |l| <= 3: 315 modes, 300 disc points, 8 toroidal planes, 2 sets."""
+    r, theta = disc_points(seed, 300)
+    return spectral3d("spectral3d_small", 8, 3, r, theta, 8, 2, seed)
+
+
+def spectral3d_L32(seed: int = 6) -> Spectral3D:
+    """n <= 32 (561 modes) x |l| <= 16: 18 513 modes; 128 CGL radii x 256 theta
+    = 32 768 polar points; 64 toroidal planes; one coefficient set."""
+    r, theta = cgl_polar_grid(128, 256)
+    return spectral3d("spectral3d_L32", 32, 16, r, theta, 64, 1, seed)
