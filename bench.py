@@ -134,6 +134,75 @@ def series_leg(steps: int, warmup: int):
     return out
 
 
+def spectral3d_leg(steps: int, warmup: int):
+    """Three-dimensional spectral series with duplicated modes (561 (n, m) pairs
+    x 33 values of l = 18 513 modes; 32 768 polar points x 64 toroidal planes):
+    forward + backward of the deduplicated path per precision, and the forward
+    of the planar series over the full duplicated mode list (coefficients
+    c_j F_{l_j}(phi_q) prepared beforehand) as the comparison."""
+    import torch
+
+    import paper_2409_19156_amd as zp
+    import zp_workloads as W
+
+    w = W.spectral3d_L32()
+    dev = torch.device("cuda:0")
+    P, Q, B = w.r.size, w.phi.size, w.c.shape[1]
+    r, th, ph = (torch.from_numpy(x).to(dev) for x in (w.r, w.theta, w.phi))
+    c, g = torch.from_numpy(w.c).to(dev), torch.from_numpy(w.g).to(dev)
+    stream = torch.cuda.current_stream(dev)
+    U = int(np.unique(np.stack([w.n, w.m]), axis=1).shape[1])
+
+    def timed(fn):
+        for _ in range(warmup):
+            res = fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            res = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps, res
+
+    out, ref = {"workload": f"spectral3d_L32: {w.J} modes = {U} (n, m) pairs x 33 l; {P} polar points "
+                            f"(128 CGL radii x 256 theta) x {Q} phi planes; {B} set; fwd+bwd (c, r, theta, phi)",
+                "modes": w.J, "distinct_pairs": U}, None
+    for prec in ("fp64", "bf16x3"):
+        full, _, cb = zp.series3d_sizes(w.n, w.m, w.l, P, Q, B, prec)
+        ws = torch.empty(full, dtype=torch.uint8, device=dev)
+        cache = torch.empty(cb, dtype=torch.uint8, device=dev)
+
+        def step():
+            f = zp.series3d_forward(w.n, w.m, w.l, r, th, ph, c, prec, cache=cache, ws=ws)
+            return (f,) + zp.series3d_backward(w.n, w.m, w.l, r, th, ph, c, g, prec, cache=cache, ws=ws)
+
+        ms, res = timed(step)
+        ms_f, _ = timed(lambda: zp.series3d_forward(w.n, w.m, w.l, r, th, ph, c, prec, cache=cache, ws=ws))
+        entry = {"ms_fwd_bwd": ms, "ms_fwd": ms_f, "gemm_gflop_dedup": 3 * 2.0 * P * U * Q * B / 1e9}
+        if prec == "fp64":
+            ref = [x.clone() for x in res]
+        else:
+            errs = [((a - b).abs().max() / b.abs().max()).item() for a, b in zip(res, ref)]
+            entry["rel_err_vs_fp64"] = dict(zip(("f", "grad_c", "grad_r", "grad_theta", "grad_phi"), errs))
+        out[prec] = entry
+        del ws, cache
+        torch.cuda.empty_cache()
+    # the same forward as a planar series over the duplicated list
+    a = np.abs(w.l)[:, None] * w.phi[None, :]
+    F = np.where(w.l[:, None] >= 0, np.cos(a), np.sin(a))
+    cq = torch.from_numpy((w.c[:, None, :] * F[:, :, None]).reshape(w.J, Q * B)).to(dev)
+    full, _, _ = zp.series_sizes(w.J, P, Q * B, "fp64")
+    ws = torch.empty(full, dtype=torch.uint8, device=dev)
+    ms_dup, f_dup = timed(lambda: zp.series_forward(w.n, w.m, r, th, cq, "fp64", ws=ws))
+    out["fp64_duplicated_planar_ms_fwd"] = ms_dup
+    out["dedup_speedup_fwd_fp64"] = ms_dup / out["fp64"]["ms_fwd"]
+    out["dedup_vs_duplicated_rel_diff"] = ((f_dup.view(P, Q, B) - ref[0]).abs().max() / ref[0].abs().max()).item()
+    del ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
@@ -213,7 +282,7 @@ def main():
                    "modes": wl.M, "points": wl.P, "outputs": 5, "entries": entries},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "chain_kernel<3,true,false>", "bytes_per_launch": bytes_per_launch,
+                     "kernel": "chain_kernel<3, true, false, 2, false>", "bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": ms * 1e3, "measured_fill_GBs": fill_gbs,
                      "frac_of_measured_fill": achieved / fill_gbs},
         "first_call_ms": first_call_ms,
@@ -221,6 +290,7 @@ def main():
     }
     if not args.no_series:
         res["series"] = series_leg(steps=max(3, min(args.steps, 10)), warmup=2)
+        res["spectral3d"] = spectral3d_leg(steps=max(3, min(args.steps, 10)), warmup=2)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_points)
     print(json.dumps(res), flush=True)

@@ -63,7 +63,8 @@ typedef enum zp_prec {
                      accumulation */
 } zp_prec;
 
-#define ZP_N_MAX 1000 /* largest radial order n accepted */
+#define ZP_N_MAX 1000    /* largest radial order n accepted */
+#define ZP_L_MAX 1048576 /* largest |l| of a toroidal Fourier index (zp_series3d_*) */
 
 /* Output selection bits of zp_basis. */
 #define ZP_Z 1u       /* Z                        */
@@ -183,6 +184,58 @@ zp_status zp_series_jvp(const int32_t *h_n, const int32_t *h_m, int64_t M, const
                         const double *d_theta, int64_t P, const double *d_c, int64_t B, int32_t prec,
                         const double *d_tc, const double *d_tr, const double *d_ttheta, double *d_tf, void *d_ws,
                         size_t ws_bytes, void *stream);
+
+/*
+ * Three-dimensional spectral series (the paper's duplicated-mode use, Sec. 3
+ * footnote): a Zernike basis on the polar plane times a Fourier basis in a
+ * periodic third coordinate phi,
+ *   f[p][q][b] = sum_j c[j][b] R_{n_j}^{|m_j|}(r_p) F_{m_j}(theta_p) F_{l_j}(phi_q),
+ * where F_m(theta) is the angular factor of Eq. (zernike-poly) and
+ * F_l(phi) = cos(l phi) for l >= 0, sin(|l| phi) for l < 0.  Points form a
+ * tensor grid: P polar points (r_p, theta_p) times Q angles phi_q.
+ *
+ * Modes j = 0..J-1 are triples (n_j, m_j, l_j): host int32 arrays h_n, h_m,
+ * h_l.  Modes sharing (n, m) with different l are "duplicated": their
+ * Zernike factor is evaluated once, the Fourier factor is folded into the
+ * coefficients, and the contraction runs over the U distinct (n, m) pairs
+ * (U = J / (2L+1) for every l in [-L, L]).  Any order and any repetition of
+ * triples is accepted; |l| <= ZP_L_MAX.
+ *
+ * Layouts (row-major FP64): c [J][B], f and g [P][Q][B], phi [Q].
+ * Workspace: zp_series3d_workspace() reports the size for one pass and the
+ * minimum (smaller sizes process the points in chunks); 256-byte aligned.
+ * The basis cache (zp_series3d_cache_bytes) works as for the planar series:
+ * filled by the forward, used by the backward if non-NULL, valid only for the
+ * same modes, polar points and prec.
+ * J == 0, P == 0, Q == 0 or B == 0 is a successful no-op.
+ * Errors: as zp_series_fwd; ZP_ERR_MODE also for |l| > ZP_L_MAX.
+ */
+zp_status zp_series3d_workspace(const int32_t *h_n, const int32_t *h_m, const int32_t *h_l, int64_t J, int64_t P,
+                                int64_t Q, int64_t B, int32_t prec, size_t *full_bytes, size_t *min_bytes);
+zp_status zp_series3d_cache_bytes(const int32_t *h_n, const int32_t *h_m, const int32_t *h_l, int64_t J, int64_t P,
+                                  int32_t prec, size_t *bytes);
+
+/* zp_series3d_fwd -- f = the series above; d_f [P][Q][B] is overwritten. */
+zp_status zp_series3d_fwd(const int32_t *h_n, const int32_t *h_m, const int32_t *h_l, int64_t J, const double *d_r,
+                          const double *d_theta, int64_t P, const double *d_phi, int64_t Q, const double *d_c,
+                          int64_t B, int32_t prec, double *d_f, void *d_cache, void *d_ws, size_t ws_bytes,
+                          void *stream);
+
+/*
+ * zp_series3d_bwd -- adjoint of zp_series3d_fwd for an upstream gradient
+ * g = dL/df [P][Q][B]:
+ *   grad_c[j][b]   = sum_p sum_q Z_j(p) F_{l_j}(phi_q) g[p][q][b]
+ *   grad_r[p]      = sum_q sum_b g[p][q][b] sum_j dZ_j/dr(p) F_{l_j}(phi_q) c[j][b]
+ *   grad_theta[p]  likewise with dZ_j/dtheta
+ *   grad_phi[q]    = sum_p sum_b g[p][q][b] sum_j Z_j(p) dF_{l_j}/dphi(phi_q) c[j][b]
+ * Each output is nullable (not computed when NULL) and overwritten.  Sums
+ * have a fixed order: repeated calls are bitwise equal.
+ */
+zp_status zp_series3d_bwd(const int32_t *h_n, const int32_t *h_m, const int32_t *h_l, int64_t J, const double *d_r,
+                          const double *d_theta, int64_t P, const double *d_phi, int64_t Q, const double *d_c,
+                          int64_t B, int32_t prec, const double *d_g, const void *d_cache, double *d_grad_c,
+                          double *d_grad_r, double *d_grad_theta, double *d_grad_phi, void *d_ws, size_t ws_bytes,
+                          void *stream);
 
 /* Static description of a status code. */
 const char *zp_status_string(zp_status s);

@@ -161,6 +161,8 @@ def series_forward(n, m, r, theta, c, prec="fp64", cache: torch.Tensor | None = 
     c = _coef(c, M)
     B = c.shape[1]
     f = torch.empty((P, B), dtype=torch.float64, device=r.device)
+    if M == 0 or P == 0 or B == 0:  # an empty sum (the library call is a no-op)
+        return f.zero_()
     if ws is None:
         ws = _workspace(M, P, B, prec, _budget(mem_budget), r.device)
     with torch.cuda.device(r.device):
@@ -285,3 +287,136 @@ def series(c, r, theta, n, m, prec="fp64", mem_budget=None):
 
 
 __all__ += ["series_sizes", "series_forward", "series_backward", "series_jvp", "ZernikeSeries", "series"]
+
+
+# ---------------------------------------------------- three-dimensional --
+
+def modes3_i32(n, m, l):
+    nh, mh = modes_i32(n, m)
+    if isinstance(l, torch.Tensor):
+        l = l.detach().cpu().numpy()
+    lh = np.ascontiguousarray(l, dtype=np.int32).reshape(-1)
+    if lh.shape != nh.shape:
+        raise ValueError("n, m and l must have the same length")
+    return nh, mh, lh
+
+
+def series3d_sizes(n, m, l, P: int, Q: int, B: int, prec="fp64"):
+    """(workspace bytes for one pass, minimum workspace bytes, basis-cache bytes)
+    of the three-dimensional series."""
+    import ctypes
+
+    lib = _lib.load()
+    nh, mh, lh = modes3_i32(n, m, l)
+    full, mn, cb = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    _lib.check(lib.zp_series3d_workspace(nh.ctypes.data, mh.ctypes.data, lh.ctypes.data, nh.size, P, Q, B,
+                                         _prec_code(prec), ctypes.byref(full), ctypes.byref(mn)),
+               "zp_series3d_workspace")
+    _lib.check(lib.zp_series3d_cache_bytes(nh.ctypes.data, mh.ctypes.data, lh.ctypes.data, nh.size, P,
+                                           _prec_code(prec), ctypes.byref(cb)), "zp_series3d_cache_bytes")
+    return full.value, mn.value, cb.value
+
+
+def _workspace3(nh, mh, lh, P, Q, B, prec, budget, device):
+    full, mn, _ = series3d_sizes(nh, mh, lh, P, Q, B, prec)
+    nbytes = full if full <= budget else max(mn, budget)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def series3d_forward(n, m, l, r, theta, phi, c, prec="fp64", cache: torch.Tensor | None = None,
+                     ws: torch.Tensor | None = None, mem_budget=None) -> torch.Tensor:
+    """f[p, q, b] = sum_j c[j, b] Z_{n_j m_j}(r_p, theta_p) F_{l_j}(phi_q), with
+    F_l(phi) = cos(l phi) (l >= 0) or sin(|l| phi) (l < 0).  Modes sharing (n, m)
+    share one Zernike evaluation."""
+    lib = _lib.load()
+    nh, mh, lh = modes3_i32(n, m, l)
+    r, theta, phi = _points(r, "r"), _points(theta, "theta"), _points(phi, "phi")
+    J, P, Q = nh.size, r.numel(), phi.numel()
+    c = _coef(c, J)
+    B = c.shape[1]
+    f = torch.empty((P, Q, B), dtype=torch.float64, device=r.device)
+    if J == 0 or P == 0 or Q == 0 or B == 0:
+        return f.zero_()
+    if ws is None:
+        ws = _workspace3(nh, mh, lh, P, Q, B, prec, _budget(mem_budget), r.device)
+    with torch.cuda.device(r.device):
+        st = lib.zp_series3d_fwd(nh.ctypes.data, mh.ctypes.data, lh.ctypes.data, J, r.data_ptr(), theta.data_ptr(), P,
+                                 phi.data_ptr(), Q, c.data_ptr(), B, _prec_code(prec), f.data_ptr(),
+                                 cache.data_ptr() if cache is not None else None, ws.data_ptr(), ws.numel(),
+                                 _stream(r.device))
+    _lib.check(st, "zp_series3d_fwd")
+    return f
+
+
+def series3d_backward(n, m, l, r, theta, phi, c, g, prec="fp64", cache: torch.Tensor | None = None,
+                      need=(True, True, True, True), ws: torch.Tensor | None = None, mem_budget=None):
+    """(dL/dc, dL/dr, dL/dtheta, dL/dphi) for g = dL/df [P, Q, B]; entries not
+    in ``need`` are None."""
+    lib = _lib.load()
+    nh, mh, lh = modes3_i32(n, m, l)
+    r, theta, phi = _points(r, "r"), _points(theta, "theta"), _points(phi, "phi")
+    J, P, Q = nh.size, r.numel(), phi.numel()
+    c = _coef(c, J)
+    B = c.shape[1]
+    g = g.contiguous()
+    if g.shape != (P, Q, B) or g.dtype != torch.float64:
+        raise ValueError("g must be float64 [P, Q, B]")
+    dev = r.device
+    outs = [torch.empty(shape, dtype=torch.float64, device=dev) if want else None
+            for want, shape in zip(need, ((J, B), (P,), (P,), (Q,)))]
+    if J == 0 or P == 0 or Q == 0 or B == 0:
+        return tuple(None if x is None else x.zero_() for x in outs)
+    if ws is None:
+        ws = _workspace3(nh, mh, lh, P, Q, B, prec, _budget(mem_budget), dev)
+    ptr = (lambda t: t.data_ptr() if t is not None else None)
+    with torch.cuda.device(dev):
+        st = lib.zp_series3d_bwd(nh.ctypes.data, mh.ctypes.data, lh.ctypes.data, J, r.data_ptr(), theta.data_ptr(), P,
+                                 phi.data_ptr(), Q, c.data_ptr(), B, _prec_code(prec), g.data_ptr(), ptr(cache),
+                                 *(ptr(x) for x in outs), ws.data_ptr(), ws.numel(), _stream(dev))
+    _lib.check(st, "zp_series3d_bwd")
+    return tuple(outs)
+
+
+class ZernikeSeries3D(torch.autograd.Function):
+    """f = sum_j c_j Z_{n_j m_j}(r, theta) F_{l_j}(phi) on a (polar points) x
+    (phi) grid, with the hand-written adjoint zp_series3d_bwd.  The basis of
+    the distinct (n, m) pairs is kept from the forward when it fits the
+    memory budget."""
+
+    @staticmethod
+    def forward(ctx, c, r, theta, phi, n, m, l, prec="fp64", mem_budget=None):
+        nh, mh, lh = modes3_i32(n, m, l)
+        J, P, Q, B = nh.size, r.numel(), phi.numel(), c.shape[1]
+        budget = _budget(mem_budget)
+        cache = None
+        if J and P and Q and B:
+            _, _, cache_bytes = series3d_sizes(nh, mh, lh, P, Q, B, prec)
+            if cache_bytes <= budget:
+                cache = torch.empty(cache_bytes, dtype=torch.uint8, device=r.device)
+        f = series3d_forward(nh, mh, lh, r, theta, phi, c, prec, cache=cache, mem_budget=budget)
+        ctx.modes = (nh, mh, lh)
+        ctx.prec = prec
+        ctx.budget = budget
+        ctx.cache = cache
+        ctx.save_for_backward(c, r, theta, phi)
+        return f
+
+    @staticmethod
+    def backward(ctx, g):
+        c, r, theta, phi = ctx.saved_tensors
+        nh, mh, lh = ctx.modes
+        need = ctx.needs_input_grad[:4]
+        gc, gr, gt, gp = series3d_backward(nh, mh, lh, r, theta, phi, c, g, ctx.prec, cache=ctx.cache, need=need,
+                                           mem_budget=ctx.budget)
+        gr = gr.view_as(r) if gr is not None else None
+        gt = gt.view_as(theta) if gt is not None else None
+        gp = gp.view_as(phi) if gp is not None else None
+        return gc, gr, gt, gp, None, None, None, None, None
+
+
+def series3d(c, r, theta, phi, n, m, l, prec="fp64", mem_budget=None):
+    """Differentiable three-dimensional spectral series f[p, q, b]."""
+    return ZernikeSeries3D.apply(c, r, theta, phi, n, m, l, prec, mem_budget)
+
+
+__all__ += ["series3d_sizes", "series3d_forward", "series3d_backward", "ZernikeSeries3D", "series3d"]

@@ -128,7 +128,11 @@ const char *zp_status_string(zp_status s)
 
 const char *zp_last_error(void) { return t_last_error.c_str(); }
 
-void zp_cache_clear(void) { clear_plans(); }
+void zp_cache_clear(void)
+{
+    clear_plans();
+    clear_plans3();
+}
 
 int32_t zp_abi_version(void) { return 1; }
 

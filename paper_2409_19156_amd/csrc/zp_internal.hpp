@@ -108,6 +108,7 @@ std::shared_ptr<Plan> build_plan_host(const int32_t *n, const int32_t *m, int64_
 // Cached plan for the current device, uploaded on first use.
 zp_status get_plan(const int32_t *n, const int32_t *m, int64_t M, std::shared_ptr<Plan> *out);
 void clear_plans();
+void clear_plans3(); // three-dimensional series tables (series3d.cpp)
 
 // ------------------------------------------------------------- outputs --
 

@@ -133,3 +133,34 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         _lib.load()
+
+
+def test_series3d_validation(lib):
+    n, m = _modes([2, 3, 2], [0, -1, 0])
+    l = np.ascontiguousarray([0, 1, -1], dtype=np.int32)
+    nd, md, ld = n.ctypes.data, m.ctypes.data, l.ctypes.data
+    full, mn, cb = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.zp_series3d_workspace(nd, md, ld, 3, 100, 8, 2, 0, ctypes.byref(full), ctypes.byref(mn)) == OK
+    assert 0 < mn.value <= full.value and full.value % 256 == 0
+    # two distinct (n, m) pairs: the cache is the planar cache of those two
+    ref = ctypes.c_size_t()
+    assert lib.zp_series3d_cache_bytes(nd, md, ld, 3, 100, 0, ctypes.byref(cb)) == OK
+    assert lib.zp_series_cache_bytes(2, 100, 0, ctypes.byref(ref)) == OK and cb.value == ref.value
+    bad_l = np.ascontiguousarray([0, 1, 1048577], dtype=np.int32)
+    args = (FAKE, FAKE, 4, FAKE, 2, FAKE, 2)
+    assert lib.zp_series3d_fwd(nd, md, bad_l.ctypes.data, 3, *args, 0, FAKE, None, FAKE, 1 << 20, None) == ERR_MODE
+    assert b"ZP_L_MAX" in lib.zp_last_error()
+    bad_n, _ = _modes([2, 4, 2], [0, -1, 0])
+    assert lib.zp_series3d_fwd(bad_n.ctypes.data, md, ld, 3, *args, 0, FAKE, None, FAKE, 1 << 20, None) == ERR_MODE
+    assert lib.zp_series3d_bwd(bad_n.ctypes.data, md, ld, 3, *args, 0, FAKE, None, FAKE, FAKE, FAKE, FAKE, FAKE,
+                               1 << 20, None) == ERR_MODE
+    assert lib.zp_series3d_fwd(nd, md, None, 3, *args, 0, FAKE, None, FAKE, 1 << 20, None) == ERR_ARG
+    assert lib.zp_series3d_fwd(nd, md, ld, 3, *args, 7, FAKE, None, FAKE, 1 << 20, None) == ERR_PREC
+    assert lib.zp_series3d_fwd(nd, md, ld, 3, FAKE, FAKE, 4, None, 2, FAKE, 2, 0, FAKE, None, FAKE, 1 << 20,
+                               None) == ERR_ARG
+    assert lib.zp_series3d_fwd(nd, md, ld, 3, *args, 0, FAKE, None, FAKE, 16, None) == ERR_WS
+    assert lib.zp_series3d_fwd(nd, md, ld, 3, FAKE, FAKE, 4, FAKE, -2, FAKE, 2, 0, FAKE, None, FAKE, 1 << 20,
+                               None) == ERR_ARG
+    # empty problems are no-ops
+    assert lib.zp_series3d_fwd(nd, md, ld, 3, FAKE, FAKE, 4, FAKE, 0, FAKE, 2, 0, FAKE, None, FAKE, 0, None) == OK
+    assert lib.zp_series3d_fwd(nd, md, ld, 0, FAKE, FAKE, 4, FAKE, 2, FAKE, 2, 0, FAKE, None, FAKE, 0, None) == OK
