@@ -13,6 +13,10 @@ does, and this package imports nothing from it.
 * ``series_*`` -- the Zernike series f = sum_k c_k Z_k (Eq. zernike-poly
   summed over modes) and its exact adjoint, as plain float64 matrix products
   on the oracle basis rounded to double.
+* ``analysis_grid`` / ``analysis`` -- coefficients from samples by
+  quadrature, c_k = (1/N_k) sum_p w_p Z_k(p) f_p with N_k the integral of
+  Z_k^2 over the unit disc (orthogonality of the basis); the rule is
+  Gauss-Legendre in r^2 (numpy's routine) times the trapezoidal rule in theta.
 * ``fourier`` / ``series3d_*`` -- the three-dimensional spectral series of the
   paper's duplicated-mode use (Sec. 3, footnote): modes (n, m, l), value
   sum_j c_j R_n^m(r) F_m(theta) F_l(phi) with F the Fourier basis, evaluated
@@ -208,3 +212,29 @@ def series3d_bwd(Z, Zr, Zt, F, dF, c, g):
     grad_t = np.einsum("pqb,jp,jq,jb->p", g, Zt, F, c, optimize=True)
     grad_phi = np.einsum("pqb,jp,jq,jb->q", g, Z, dF, c, optimize=True)
     return grad_c, grad_r, grad_t, grad_phi
+
+
+def mode_norms(n, m):
+    """N_k = integral of Z_k^2 over the unit disc: the radial integral
+    1 / (2 (n + 1)) times pi (m != 0) or 2 pi (m = 0)."""
+    n = np.asarray(n, dtype=np.float64)
+    m = np.asarray(m)
+    return np.where(m == 0, 2.0, 1.0) * np.pi / (2.0 * (n + 1.0))
+
+
+def analysis_grid(nr: int, nt: int):
+    """Quadrature on the disc: Gauss-Legendre nodes x in t = r^2 = (1 + x)/2,
+    times nt equispaced angles; point p = i * nt + j.  Returns (r, theta, w)."""
+    x, wx = np.polynomial.legendre.leggauss(nr)
+    t = (1.0 + x) / 2.0
+    th = 2.0 * np.pi * np.arange(nt) / nt
+    r = np.repeat(np.sqrt(t), nt)
+    theta = np.tile(th, nr)
+    # r dr = dt / 2 and dt = dx / 2; the angle contributes 2 pi / nt
+    w = np.repeat(wx / 4.0 * (2.0 * np.pi / nt), nt)
+    return r, theta, w
+
+
+def analysis(Z, n, m, w, f):
+    """c[k, b] = (1 / N_k) sum_p w_p Z[k, p] f[p, b]."""
+    return (np.asarray(Z) @ (np.asarray(w)[:, None] * np.asarray(f))) / mode_norms(n, m)[:, None]
