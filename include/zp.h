@@ -158,7 +158,8 @@ zp_status zp_series_fwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
  *   grad_r[p]       = sum_b g[p][b] sum_k dZ_k/dr(p) c[k][b]
  *   grad_theta[p]   = sum_b g[p][b] sum_k dZ_k/dtheta(p) c[k][b]
  * Each of d_grad_c [M*B], d_grad_r [P], d_grad_theta [P] is nullable (not
- * computed when NULL); results are overwritten, not accumulated.  Sums have
+ * computed when NULL); results are overwritten, not accumulated.  d_c is read
+ * only for grad_r / grad_theta and may be NULL when both are NULL.  Sums have
  * a fixed order (no floating-point atomics): repeated calls are bitwise equal.
  */
 zp_status zp_series_bwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r,
@@ -236,6 +237,41 @@ zp_status zp_series3d_bwd(const int32_t *h_n, const int32_t *h_m, const int32_t 
                           int64_t B, int32_t prec, const double *d_g, const void *d_cache, double *d_grad_c,
                           double *d_grad_r, double *d_grad_theta, double *d_grad_phi, void *d_ws, size_t ws_bytes,
                           void *stream);
+
+/*
+ * Analysis transform: Zernike coefficients from samples of a function on the
+ * unit disc by quadrature (the inverse of zp_series_fwd for band-limited
+ * data; the spectral-method use of the basis, Sec. 1).  The basis is
+ * orthogonal over the disc: the integral of Z_k Z_k' dA is delta_kk' N_k with
+ * N_k = eps_m pi / (2 (n_k + 1)), eps_m = 2 for m = 0 and 1 otherwise.
+ *
+ * zp_analysis_grid -- a host-side quadrature rule on nr x nt points
+ * (p = i * nt + j, theta fastest): Gauss-Legendre in t = r^2 with nr nodes
+ * times the trapezoidal rule at theta_j = 2 pi j / nt.  For modes with n <= L
+ * and data that is a series in those modes, nr >= ceil((L + 1) / 2) and
+ * nt >= 2 L + 1 make the transform exact.
+ *   h_r, h_theta, h_w  host double[nr * nt] (outputs); weights sum to pi.
+ * Errors: ZP_ERR_ARG (nr or nt < 1, nr > 2^20, nt > 2^24, null pointer).
+ */
+zp_status zp_analysis_grid(int64_t nr, int64_t nt, double *h_r, double *h_theta, double *h_w);
+
+/* Workspace of zp_series_analysis: one pass / minimum (chunked), bytes. */
+zp_status zp_series_analysis_workspace(int64_t M, int64_t P, int64_t B, int32_t prec, size_t *full_bytes,
+                                       size_t *min_bytes);
+
+/*
+ * zp_series_analysis -- c[k][b] = (1 / N_k) sum_p w_p Z_k(r_p, theta_p) f[p][b].
+ *   d_r, d_theta, d_w  device double[P]: quadrature points and weights (any
+ *                      rule; zp_analysis_grid gives an exact one)
+ *   d_f       device double[P*B], samples, row-major [P][B]
+ *   d_c       device double[M*B] (output), row-major [M][B]
+ * The contraction over points runs in prec, as zp_series_bwd's grad_c.
+ * P == 0 gives all-zero coefficients; M == 0 or B == 0 is a no-op.
+ * Errors: as zp_series_bwd.
+ */
+zp_status zp_series_analysis(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r,
+                             const double *d_theta, const double *d_w, int64_t P, const double *d_f, int64_t B,
+                             int32_t prec, double *d_c, void *d_ws, size_t ws_bytes, void *stream);
 
 /* Static description of a status code. */
 const char *zp_status_string(zp_status s);

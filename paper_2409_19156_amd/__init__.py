@@ -289,6 +289,56 @@ def series(c, r, theta, n, m, prec="fp64", mem_budget=None):
 __all__ += ["series_sizes", "series_forward", "series_backward", "series_jvp", "ZernikeSeries", "series"]
 
 
+# ------------------------------------------------------------- analysis --
+
+def analysis_grid(nr: int, nt: int):
+    """Host quadrature rule on the unit disc (numpy float64 r, theta, w of
+    nr * nt points, theta fastest): Gauss-Legendre in r^2 times the
+    trapezoidal rule in theta.  Exact for modes n <= L with
+    nr >= ceil((L+1)/2), nt >= 2L+1."""
+    lib = _lib.load()
+    P = int(nr) * int(nt)
+    r, th, w = (np.empty(max(P, 1), dtype=np.float64) for _ in range(3))
+    _lib.check(lib.zp_analysis_grid(int(nr), int(nt), r.ctypes.data, th.ctypes.data, w.ctypes.data),
+               "zp_analysis_grid")
+    return r[:P], th[:P], w[:P]
+
+
+def series_analysis(n, m, r, theta, w, f, prec="fp64", ws: torch.Tensor | None = None,
+                    mem_budget=None) -> torch.Tensor:
+    """Coefficients c[k, b] = (1/N_k) sum_p w_p Z_k(r_p, theta_p) f[p, b] from
+    samples f [P, B] with quadrature weights w [P] (N_k = integral of Z_k^2)."""
+    import ctypes
+
+    lib = _lib.load()
+    nh, mh = modes_i32(n, m)
+    r, theta, w = _points(r, "r"), _points(theta, "theta"), _points(w, "w")
+    M, P = nh.size, r.numel()
+    if not isinstance(f, torch.Tensor) or f.dtype != torch.float64 or f.dim() != 2 or f.shape[0] != P:
+        raise ValueError("f must be a float64 GPU tensor [P, B]")
+    f = f.contiguous()
+    B = f.shape[1]
+    c = torch.empty((M, B), dtype=torch.float64, device=r.device)
+    if M == 0 or B == 0:
+        return c
+    if ws is None:
+        full, mn = ctypes.c_size_t(), ctypes.c_size_t()
+        _lib.check(lib.zp_series_analysis_workspace(M, P, B, _prec_code(prec), ctypes.byref(full), ctypes.byref(mn)),
+                   "zp_series_analysis_workspace")
+        budget = _budget(mem_budget)
+        nbytes = full.value if full.value <= budget else max(mn.value, budget)
+        ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=r.device)
+    with torch.cuda.device(r.device):
+        st = lib.zp_series_analysis(nh.ctypes.data, mh.ctypes.data, M, r.data_ptr(), theta.data_ptr(), w.data_ptr(),
+                                    P, f.data_ptr(), B, _prec_code(prec), c.data_ptr(), ws.data_ptr(), ws.numel(),
+                                    _stream(r.device))
+    _lib.check(st, "zp_series_analysis")
+    return c
+
+
+__all__ += ["analysis_grid", "series_analysis"]
+
+
 # ---------------------------------------------------- three-dimensional --
 
 def modes3_i32(n, m, l):

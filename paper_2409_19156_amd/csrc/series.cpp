@@ -319,7 +319,8 @@ zp_status zp_series_bwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
     zp_status st = common_checks(h_n, h_m, M, P, B, prec);
     if (st != ZP_OK) return st;
     if (M == 0 || P == 0 || B == 0) return ZP_OK;
-    if (!d_r || !d_theta || !d_c || !d_g) return set_error(ZP_ERR_ARG, "null pointer");
+    if (!d_r || !d_theta || !d_g) return set_error(ZP_ERR_ARG, "null pointer");
+    if (!d_c && (d_grad_r || d_grad_theta)) return set_error(ZP_ERR_ARG, "null coefficients with grad_r or grad_theta");
     if (!d_ws || ((uintptr_t)d_ws & 255)) return set_error(ZP_ERR_ARG, "workspace must be non-null and 256-byte aligned");
     if (!d_grad_c && !d_grad_r && !d_grad_theta) return ZP_OK;
     if ((uintptr_t)d_cache & 255) return set_error(ZP_ERR_ARG, "cache must be 256-byte aligned");

@@ -164,3 +164,57 @@ def test_series3d_validation(lib):
     # empty problems are no-ops
     assert lib.zp_series3d_fwd(nd, md, ld, 3, FAKE, FAKE, 4, FAKE, 0, FAKE, 2, 0, FAKE, None, FAKE, 0, None) == OK
     assert lib.zp_series3d_fwd(nd, md, ld, 0, FAKE, FAKE, 4, FAKE, 2, FAKE, 2, 0, FAKE, None, FAKE, 0, None) == OK
+
+
+def test_analysis_grid_matches_oracle_rule(oracle_mod):
+    """zp_analysis_grid is host code: its Gauss-Legendre rule against numpy's
+    (accurate to ~1e-15 for up to a few tens of nodes) and, at 50 and 300
+    nodes, where numpy's rule loses digits near the ends, against nodes and
+    weights refined by Newton's method in mpmath at 40 digits."""
+    import mpmath as mp
+
+    import paper_2409_19156_amd as zp
+
+    for nr, nt in [(1, 1), (2, 5), (7, 3), (26, 101)]:
+        r, th, w = zp.analysis_grid(nr, nt)
+        ro, tho, wo = oracle_mod.analysis_grid(nr, nt)
+        assert np.abs(r - ro).max() <= 4e-16 and np.abs(th - tho).max() <= 1e-15
+        assert np.abs(w - wo).max() <= 1e-14 * np.abs(wo).max()
+        assert abs(w.sum() - np.pi) <= 1e-14
+    mp.mp.dps = 40
+    for N, i in [(50, 0), (50, 24), (50, 49), (300, 0), (300, 1), (300, 77), (300, 149), (300, 150), (300, 298),
+                 (300, 299)]:
+        r, _, w = zp.analysis_grid(N, 1)
+        x = 2 * mp.mpf(r[i]) ** 2 - 1
+        for _ in range(4):
+            p, q = mp.legendre(N, x), mp.legendre(N - 1, x)
+            x -= p / (N * (x * p - q) / (x * x - 1))
+        p, q = mp.legendre(N, x), mp.legendre(N - 1, x)
+        dp = N * (x * p - q) / (x * x - 1)
+        w_ref = 2 / ((1 - x * x) * dp * dp) / 4 * 2 * mp.pi
+        assert abs(r[i] - mp.sqrt((1 + x) / 2)) <= 2.3e-16 * r[i], (N, i)  # one ulp
+        assert abs(w[i] - w_ref) <= 2e-15 * w[i], (N, i)
+        assert abs(w.sum() - np.pi) <= 1e-13
+
+
+def test_analysis_validation(lib):
+    n, m = _modes([2, 3], [0, -1])
+    nd, md = n.ctypes.data, m.ctypes.data
+    buf = np.zeros(8)
+    p = buf.ctypes.data
+    assert lib.zp_analysis_grid(0, 4, p, p, p) == ERR_ARG
+    assert lib.zp_analysis_grid(2, 4, None, p, p) == ERR_ARG
+    full, mn = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.zp_series_analysis_workspace(2, 100, 3, 2, ctypes.byref(full), ctypes.byref(mn)) == OK
+    assert 0 < mn.value <= full.value
+    assert lib.zp_series_analysis_workspace(2, 100, 3, 9, ctypes.byref(full), None) == ERR_PREC
+    bad, _ = _modes([2, 4], [0, -1])
+    assert lib.zp_series_analysis(bad.ctypes.data, md, 2, FAKE, FAKE, FAKE, 4, FAKE, 2, 0, FAKE, FAKE, 1 << 20,
+                                  None) == ERR_MODE
+    assert lib.zp_series_analysis(nd, md, 2, FAKE, FAKE, None, 4, FAKE, 2, 0, FAKE, FAKE, 1 << 20, None) == ERR_ARG
+    assert lib.zp_series_analysis(nd, md, 2, FAKE, FAKE, FAKE, 4, FAKE, 2, 3, FAKE, FAKE, 1 << 20, None) == ERR_PREC
+    assert lib.zp_series_analysis(nd, md, 2, FAKE, FAKE, FAKE, 4, FAKE, 2, 0, FAKE, FAKE, 16, None) == ERR_WS
+    assert lib.zp_series_analysis(nd, md, 2, FAKE, FAKE, FAKE, 4, FAKE, 0, 0, FAKE, FAKE, 0, None) == OK
+    # backward: c may be NULL only when grad_r and grad_theta are not requested
+    assert lib.zp_series_bwd(nd, md, 2, FAKE, FAKE, 4, None, 2, 0, FAKE, None, None, FAKE, None, FAKE, 1 << 20,
+                             None) == ERR_ARG
