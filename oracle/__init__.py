@@ -13,6 +13,10 @@ does, and this package imports nothing from it.
 * ``series_*`` -- the Zernike series f = sum_k c_k Z_k (Eq. zernike-poly
   summed over modes) and its exact adjoint, as plain float64 matrix products
   on the oracle basis rounded to double.
+* ``series_basis2`` / ``series_bwd2`` -- second derivatives of the basis
+  (d2Z/dr2 from the quad oracle; d2Z/(dr dtheta) and d2Z/dtheta2 = -m^2 Z
+  from the quad radial derivative and long-double trigonometry) and the
+  adjoint of ``series_bwd`` (double backward), written out term by term.
 * ``analysis_grid`` / ``analysis`` -- coefficients from samples by
   quadrature, c_k = (1/N_k) sum_p w_p Z_k(p) f_p with N_k the integral of
   Z_k^2 over the unit disc (orthogonality of the basis); the rule is
@@ -166,6 +170,22 @@ def series_basis(n, m, r, theta, nthreads: int = 0):
     return basis(n, m, r, theta, MASK_Z | MASK_DR | MASK_DTHETA, nthreads=nthreads)
 
 
+def series_basis2(n, m, r, theta, nthreads: int = 0):
+    """(d2Z/dr2, d2Z/(dr dtheta), d2Z/dtheta2), each [M, P]."""
+    n = np.asarray(n)
+    m = np.asarray(m)
+    Zrr = basis(n, m, r, theta, MASK_DR2, nthreads=nthreads)[0]
+    dR = radial(n, m, r, 1, nthreads=nthreads)[1]  # dR/dr [M, P]
+    a = np.abs(m).astype(np.longdouble)[:, None]
+    arg = a * np.asarray(theta, dtype=np.float64).astype(np.longdouble)[None, :]
+    # d/dtheta of cos(a theta) = -a sin(a theta); of sin(a theta) = a cos(a theta)
+    dtrig = np.where(m[:, None] >= 0, -a * np.sin(arg), a * np.cos(arg))
+    Zrt = (dR.astype(np.longdouble) * dtrig).astype(np.float64)
+    Z = basis(n, m, r, theta, MASK_Z, nthreads=nthreads)[0]
+    Ztt = -(np.abs(m).astype(np.float64) ** 2)[:, None] * Z
+    return Zrr, Zrt, Ztt
+
+
 def series_fwd(Z, c):
     """f = Z^T c with Z [M, P] and c [M, B]: returns [P, B]."""
     return np.asarray(Z).T @ np.asarray(c)
@@ -212,6 +232,20 @@ def series3d_bwd(Z, Zr, Zt, F, dF, c, g):
     grad_t = np.einsum("pqb,jp,jq,jb->p", g, Zt, F, c, optimize=True)
     grad_phi = np.einsum("pqb,jp,jq,jb->q", g, Z, dF, c, optimize=True)
     return grad_c, grad_r, grad_t, grad_phi
+
+
+def series_bwd2(Z, Zr, Zt, Zrr, Zrt, Ztt, c, g, uc, ur, ut):
+    """Adjoint of ``series_bwd``: with L2 = <uc, grad_c> + <ur, grad_r> +
+    <ut, grad_t>, returns (dL2/dg, dL2/dc, dL2/dr, dL2/dtheta)."""
+    Z, Zr, Zt, Zrr, Zrt, Ztt, c, g, uc, ur, ut = (np.asarray(a) for a in (Z, Zr, Zt, Zrr, Zrt, Ztt, c, g, uc, ur, ut))
+    # grad_c = Z g;  grad_r[p] = sum_b g[p,b] (Zr^T c)[p,b];  grad_t likewise with Zt
+    out_g = Z.T @ uc + ur[:, None] * (Zr.T @ c) + ut[:, None] * (Zt.T @ c)
+    out_c = (Zr * ur[None, :] + Zt * ut[None, :]) @ g
+    Hu = g @ uc.T  # [P, M]
+    Hc = g @ c.T
+    out_r = np.einsum("kp,pk->p", Zr, Hu) + ur * np.einsum("kp,pk->p", Zrr, Hc) + ut * np.einsum("kp,pk->p", Zrt, Hc)
+    out_t = np.einsum("kp,pk->p", Zt, Hu) + ur * np.einsum("kp,pk->p", Zrt, Hc) + ut * np.einsum("kp,pk->p", Ztt, Hc)
+    return out_g, out_c, out_r, out_t
 
 
 def mode_norms(n, m):
