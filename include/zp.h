@@ -187,6 +187,34 @@ zp_status zp_series_jvp(const int32_t *h_n, const int32_t *h_m, int64_t M, const
                         size_t ws_bytes, void *stream);
 
 /*
+ * zp_series_bwd2 -- adjoint of zp_series_bwd, for second-order derivatives
+ * (double backward, Hessian-vector products; the paper's Hessian use of the
+ * automatic differentiation, Sec. 3).  Given cotangents uc [M*B], ur [P],
+ * ut [P] of zp_series_bwd's outputs (grad_c, grad_r, grad_theta) for the same
+ * (modes, r, theta, c, g), it returns the derivatives of
+ *   L2 = <uc, grad_c> + <ur, grad_r> + <ut, grad_theta>
+ * with respect to g, c, r and theta:
+ *   out_g[p][b] = sum_k Z_k(p) uc[k][b] + sum_k D_k(p) c[k][b]
+ *   out_c[k][b] = sum_p D_k(p) g[p][b]
+ *   out_r[p]    = sum_b g[p][b] sum_k (dZ_k/dr(p) uc[k][b] + Er_k(p) c[k][b])
+ *   out_t[p]    = sum_b g[p][b] sum_k (dZ_k/dtheta(p) uc[k][b] + Et_k(p) c[k][b])
+ * with D = ur dZ/dr + ut dZ/dtheta, Er = ur d2Z/dr2 + ut d2Z/(dr dtheta),
+ * Et = ur d2Z/(dr dtheta) + ut d2Z/dtheta2 (d2Z/dtheta2 = -m^2 Z).
+ *   d_c, d_g  device double[M*B], [P*B] (required)
+ *   d_uc, d_ur, d_ut  nullable cotangents (NULL = zero)
+ *   d_out_g [P*B], d_out_c [M*B], d_out_r [P], d_out_t [P]: nullable outputs,
+ *             overwritten
+ * Contractions run in prec.  Workspace: zp_series_bwd2_workspace (one pass /
+ * minimum).  Sums have a fixed order.  Errors: as zp_series_bwd.
+ */
+zp_status zp_series_bwd2_workspace(int64_t M, int64_t P, int64_t B, int32_t prec, size_t *full_bytes,
+                                   size_t *min_bytes);
+zp_status zp_series_bwd2(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r, const double *d_theta,
+                         int64_t P, const double *d_c, int64_t B, int32_t prec, const double *d_g, const double *d_uc,
+                         const double *d_ur, const double *d_ut, double *d_out_g, double *d_out_c, double *d_out_r,
+                         double *d_out_t, void *d_ws, size_t ws_bytes, void *stream);
+
+/*
  * Three-dimensional spectral series (the paper's duplicated-mode use, Sec. 3
  * footnote): a Zernike basis on the polar plane times a Fourier basis in a
  * periodic third coordinate phi,

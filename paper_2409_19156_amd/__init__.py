@@ -235,9 +235,77 @@ def series_jvp(n, m, r, theta, c, tc=None, tr=None, ttheta=None, prec="fp64", ws
     return tf
 
 
+def series_backward2(n, m, r, theta, c, g, uc=None, ur=None, ut=None, prec="fp64", need=(True, True, True, True),
+                     ws: torch.Tensor | None = None, mem_budget=None):
+    """Adjoint of ``series_backward`` (second-order derivatives): for cotangents
+    (uc, ur, ut) of its outputs (dL/dc, dL/dr, dL/dtheta), returns the
+    derivatives of <uc, dL/dc> + <ur, dL/dr> + <ut, dL/dtheta> with respect to
+    (g, c, r, theta); entries not in ``need`` are None, missing cotangents
+    count as zero."""
+    import ctypes
+
+    lib = _lib.load()
+    nh, mh = modes_i32(n, m)
+    r, theta = _points(r, "r"), _points(theta, "theta")
+    M, P = nh.size, r.numel()
+    c = _coef(c, M)
+    B = c.shape[1]
+    g = g.contiguous()
+    if g.shape != (P, B) or g.dtype != torch.float64:
+        raise ValueError("g must be float64 [P, B]")
+    if uc is not None:
+        uc = _coef(uc, M)
+    ur = _points(ur, "ur") if ur is not None else None
+    ut = _points(ut, "ut") if ut is not None else None
+    dev = r.device
+    outs = [torch.empty(shape, dtype=torch.float64, device=dev) if want else None
+            for want, shape in zip(need, ((P, B), (M, B), (P,), (P,)))]
+    if M == 0 or P == 0 or B == 0:
+        return tuple(None if x is None else x.zero_() for x in outs)
+    if ws is None:
+        full, mn = ctypes.c_size_t(), ctypes.c_size_t()
+        _lib.check(lib.zp_series_bwd2_workspace(M, P, B, _prec_code(prec), ctypes.byref(full), ctypes.byref(mn)),
+                   "zp_series_bwd2_workspace")
+        budget = _budget(mem_budget)
+        nbytes = full.value if full.value <= budget else max(mn.value, budget)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    ptr = (lambda t: t.data_ptr() if t is not None else None)
+    with torch.cuda.device(dev):
+        st = lib.zp_series_bwd2(nh.ctypes.data, mh.ctypes.data, M, r.data_ptr(), theta.data_ptr(), P, c.data_ptr(), B,
+                                _prec_code(prec), g.data_ptr(), ptr(uc), ptr(ur), ptr(ut), *(ptr(x) for x in outs),
+                                ws.data_ptr(), ws.numel(), _stream(dev))
+    _lib.check(st, "zp_series_bwd2")
+    return tuple(outs)
+
+
+class _SeriesBackward(torch.autograd.Function):
+    """(c, r, theta, g) -> (dL/dc, dL/dr, dL/dtheta) of the series, itself
+    differentiable through zp_series_bwd2 (double backward)."""
+
+    @staticmethod
+    def forward(ctx, c, r, theta, g, modes, prec, cache, budget, need):
+        nh, mh = modes
+        ctx.set_materialize_grads(False)
+        ctx.modes, ctx.prec, ctx.budget = modes, prec, budget
+        ctx.save_for_backward(c, r, theta, g)
+        return series_backward(nh, mh, r, theta, c, g, prec, cache=cache, need=need, mem_budget=budget)
+
+    @staticmethod
+    def backward(ctx, uc, ur, ut):
+        c, r, theta, g = ctx.saved_tensors
+        nh, mh = ctx.modes
+        nc, nr, nt, ng = ctx.needs_input_grad[:4]
+        if uc is None and ur is None and ut is None:
+            return (None,) * 9
+        og, oc, orr, ot = series_backward2(nh, mh, r, theta, c, g, uc, ur, ut, ctx.prec, need=(ng, nc, nr, nt),
+                                           mem_budget=ctx.budget)
+        return oc, orr, ot, og, None, None, None, None, None
+
+
 class ZernikeSeries(torch.autograd.Function):
-    """f = Z(r, theta)^T c with a hand-written adjoint (zp_series_bwd) and
-    forward-mode rule (zp_series_jvp).
+    """f = Z(r, theta)^T c with a hand-written adjoint (zp_series_bwd), its
+    own adjoint for second derivatives (zp_series_bwd2), and a forward-mode
+    rule (zp_series_jvp).
 
     The basis (Z, dZ/dr, dZ/dtheta) is kept from the forward when its size is
     within the memory budget, and recomputed chunk by chunk in the backward
@@ -264,10 +332,9 @@ class ZernikeSeries(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         c, r, theta = ctx.saved_tensors
-        nh, mh = ctx.modes
-        need = ctx.needs_input_grad[:3]
-        gc, gr, gt = series_backward(nh, mh, r, theta, c, g, ctx.prec, cache=ctx.cache, need=need,
-                                     mem_budget=ctx.budget)
+        need = tuple(bool(x) for x in ctx.needs_input_grad[:3])
+        gc, gr, gt = _SeriesBackward.apply(c, r, theta, g.contiguous(), ctx.modes, ctx.prec, ctx.cache, ctx.budget,
+                                           need)
         if gr is not None:
             gr = gr.view_as(r)
         if gt is not None:
@@ -286,7 +353,8 @@ def series(c, r, theta, n, m, prec="fp64", mem_budget=None):
     return ZernikeSeries.apply(c, r, theta, n, m, prec, mem_budget)
 
 
-__all__ += ["series_sizes", "series_forward", "series_backward", "series_jvp", "ZernikeSeries", "series"]
+__all__ += ["series_sizes", "series_forward", "series_backward", "series_backward2", "series_jvp", "ZernikeSeries",
+            "series"]
 
 
 # ------------------------------------------------------------- analysis --

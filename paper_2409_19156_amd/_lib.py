@@ -18,9 +18,10 @@ STATUS_NAMES = {0: "ZP_OK", 1: "ZP_ERR_MODE", 2: "ZP_ERR_ARG", 3: "ZP_ERR_ORDER"
 
 # Every symbol include/zp.h declares.
 EXPORTS = ("zp_radial", "zp_radial_direct", "zp_basis", "zp_series_workspace", "zp_series_cache_bytes", "zp_series_fwd",
-           "zp_series_bwd", "zp_series_jvp", "zp_series3d_workspace", "zp_series3d_cache_bytes", "zp_series3d_fwd",
-           "zp_series3d_bwd", "zp_analysis_grid", "zp_series_analysis_workspace", "zp_series_analysis",
-           "zp_status_string", "zp_last_error", "zp_cache_clear", "zp_abi_version")
+           "zp_series_bwd", "zp_series_jvp", "zp_series_bwd2_workspace", "zp_series_bwd2", "zp_series3d_workspace",
+           "zp_series3d_cache_bytes", "zp_series3d_fwd", "zp_series3d_bwd", "zp_analysis_grid",
+           "zp_series_analysis_workspace", "zp_series_analysis", "zp_status_string", "zp_last_error", "zp_cache_clear",
+           "zp_abi_version")
 
 
 class ZpError(RuntimeError):
@@ -50,6 +51,8 @@ def load() -> ctypes.CDLL:
         "zp_series_fwd": [vp, vp, i64, vp, vp, i64, vp, i64, i32, vp, vp, vp, sz, vp],
         "zp_series_bwd": [vp, vp, i64, vp, vp, i64, vp, i64, i32, vp, vp, vp, vp, vp, vp, sz, vp],
         "zp_series_jvp": [vp, vp, i64, vp, vp, i64, vp, i64, i32, vp, vp, vp, vp, vp, sz, vp],
+        "zp_series_bwd2_workspace": [i64, i64, i64, i32, szp, szp],
+        "zp_series_bwd2": [vp, vp, i64, vp, vp, i64, vp, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp],
         "zp_series3d_workspace": [vp, vp, vp, i64, i64, i64, i64, i32, szp, szp],
         "zp_series3d_cache_bytes": [vp, vp, vp, i64, i64, i32, szp],
         "zp_series3d_fwd": [vp, vp, vp, i64, vp, vp, i64, vp, i64, vp, i64, i32, vp, vp, vp, sz, vp],

@@ -136,7 +136,7 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 
 // NPL points per lane (1, or 2 for FP64-only outputs: each store then writes
 // 16 bytes per lane, 1 KB per wave).
-template <int J, bool ANG, bool KB, int NPL, bool DIR>
+template <int J, bool ANG, bool KB, int NPL, bool DIR, bool SEC>
 __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__ chains,
                                                        const Coef *__restrict__ coefs,
                                                        const Emit *__restrict__ emits,
@@ -146,6 +146,7 @@ __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__
 {
     static_assert(NPL == 1 || (NPL == 2 && !KB), "two points per lane only for plain FP64 planes");
     static_assert(!DIR || (ANG && J >= 1), "the directional derivative needs the basis and dZ/dr");
+    static_assert(!SEC || (DIR && J >= 2 && NPL == 1 && !KB), "second-order planes need d2Z/dr2, one point per lane");
     __shared__ Coef tab[kTabChunk];
 
     const Chain ch = chains[blockIdx.y];
@@ -218,7 +219,7 @@ __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__
             ++e;
             nextK = e < e_end ? emits[e].K : INT_MAX;
             const bool is_sin = em.flags & 1;
-            double val[5][NPL], vdir[NPL];
+            double val[5][NPL], vdir[NPL], vsr[NPL], vst[NPL];
 #pragma unroll
             for (int u = 0; u < NPL; ++u) {
                 // g^(j) = d^j/dr^j v(s(r))
@@ -244,6 +245,15 @@ __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__
                 const double fa = (double)alpha;
                 val[4][u] = ANG ? (is_sin ? fa * R[0] * cs[u] : -fa * R[0] * sn[u]) : 0.0;
                 vdir[u] = DIR ? __builtin_fma(tr[u], val[J >= 1 ? 1 : 0][u], tt[u] * val[4][u]) : 0.0;
+                if (SEC) {
+                    // d2Z/(dr dtheta) = d/dtheta of R' cos|sin; d2Z/dtheta2 = -m^2 Z
+                    const double zrt = is_sin ? fa * R[J >= 1 ? 1 : 0] * cs[u] : -fa * R[J >= 1 ? 1 : 0] * sn[u];
+                    const double ztt = -fa * fa * val[0][u];
+                    vsr[u] = __builtin_fma(tr[u], val[J >= 2 ? 2 : 0][u], tt[u] * zrt);
+                    vst[u] = __builtin_fma(tr[u], zrt, tt[u] * ztt);
+                } else {
+                    vsr[u] = vst[u] = 0.0;
+                }
             }
             const int64_t idx = (int64_t)em.col * out.ld + p0;
             if (NPL == 2) {
@@ -271,6 +281,8 @@ __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__
             if (ANG && out.plane[4]) store_plane(out, 4, idx, val[4][0]);
             // the series' bf16 path keeps only the k-blocked copy (out.dir null)
             if (DIR && out.dir) store_fmt(out.dir, out.dir_fmt, out.sub, idx, vdir[0]);
+            if (SEC && out.sec_r) store_fmt(out.sec_r, out.sec_fmt, out.sub, idx, vsr[0]);
+            if (SEC && out.sec_t) store_fmt(out.sec_t, out.sec_fmt, out.sub, idx, vst[0]);
             if (KB) {
                 const int g8 = eidx & ~7;
                 const bool full = g8 >= ch.emit_off && g8 + 8 <= e_end;
@@ -312,7 +324,7 @@ __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__
 // resident slot on 256 CUs, so the heaviest chains do not form a tail.
 constexpr int64_t kMinWorkgroups = 8192;
 
-template <int J, bool ANG, bool KB, int NPL, bool DIR = false>
+template <int J, bool ANG, bool KB, int NPL, bool DIR = false, bool SEC = false>
 hipError_t launch(const Plan &plan, const double *r, const double *th, int64_t P, const Planes &o, hipStream_t s)
 {
     const int64_t tiles = (P + (int64_t)kBlock * NPL - 1) / ((int64_t)kBlock * NPL);
@@ -320,7 +332,7 @@ hipError_t launch(const Plan &plan, const double *r, const double *th, int64_t P
     const Chain *list = use_pieces ? plan.d_pieces : plan.d_chains;
     const size_t count = use_pieces ? plan.pieces.size() : plan.chains.size();
     const dim3 grid((unsigned)tiles, (unsigned)count);
-    hipLaunchKernelGGL((chain_kernel<J, ANG, KB, NPL, DIR>), grid, dim3(kBlock), 0, s, list, plan.d_coefs, plan.d_emits,
+    hipLaunchKernelGGL((chain_kernel<J, ANG, KB, NPL, DIR, SEC>), grid, dim3(kBlock), 0, s, list, plan.d_coefs, plan.d_emits,
                        r, th, P, o);
     return hipGetLastError();
 }
@@ -344,6 +356,13 @@ zp_status launch_chain_kernel(const Plan &plan, const double *d_r, const double 
     if ((P + kBlock - 1) / kBlock > (int64_t)INT_MAX) return set_error(ZP_ERR_ARG, "too many points for one launch");
     hipError_t e;
     const bool dir = out.dir || out.kb_dir;
+    const bool sec = out.sec_r || out.sec_t;
+    if (sec) { // second-order planes (with the plain planes and dir): J = 2, one point per lane
+        if (!angular || J != 2 || out.kb || out.kb_dir)
+            return set_error(ZP_ERR_ARG, "internal: second-order output needs the basis, J = 2, no k-blocked copy");
+        e = launch<2, true, false, 1, true, true>(plan, d_r, d_theta, P, out, s);
+        return hip_check(e, "chain_kernel launch");
+    }
     if (dir && (!angular || J != 1)) return set_error(ZP_ERR_ARG, "internal: directional output needs the basis, J = 1");
     if (out.kb || out.kb_dir) { // series: k-blocked copies of Z and / or its directional derivative
         if (!angular || J > 1) return set_error(ZP_ERR_ARG, "internal: k-blocked output needs the basis, J <= 1");

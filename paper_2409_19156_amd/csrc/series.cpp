@@ -524,3 +524,232 @@ extern "C" zp_status zp_series_jvp(const int32_t *h_n, const int32_t *h_m, int64
     }
     return ZP_OK;
 }
+
+// ------------------------------------------------------- second order --
+//
+// zp_series_bwd2: the adjoint of zp_series_bwd (for double backward /
+// Hessian-vector products).  For cotangents (uc, ur, ut) of its outputs
+// (grad_c, grad_r, grad_theta), with D = ur dZ/dr + ut dZ/dtheta and
+//   Er = ur d2Z/dr2 + ut d2Z/(dr dtheta),  Et = ur d2Z/(dr dtheta) + ut d2Z/dtheta2,
+// the derivatives of L2 = <uc, grad_c> + <ur, grad_r> + <ut, grad_theta> are
+//   dL2/dg     = Z^T uc + D^T c                        (zp_series_jvp)
+//   dL2/dc     = D g                                   (split-K, as grad_c)
+//   dL2/dr[p]  = sum_k dZ/dr_k(p) (g uc^T)[p][k] + sum_k Er_k(p) (g c^T)[p][k]
+//   dL2/dth[p] = sum_k dZ/dth_k(p) (g uc^T)[p][k] + sum_k Et_k(p) (g c^T)[p][k]
+// The last two are two row-dot contractions whose per-tile partials sit one
+// after the other and are reduced together in a fixed order.
+
+namespace {
+
+struct Bwd2Layout {
+    int64_t Mp, Bp, Pcp;
+    int S, T;
+    size_t c_off, u_off, d_off, zr_off, zt_off, er_off, et_off, g_off, gt_off, pc_off, pr_off, total;
+    Bwd2Layout(int64_t M, int64_t Pc, int64_t B, int ct)
+    {
+        Mp = pad_up(M);
+        Bp = pad_up(B);
+        Pcp = pad_up(Pc);
+        const size_t e = ct_bytes(ct), dsz = dsize_of(ct);
+        S = splits_for(M, B, Pcp, ct);
+        T = (int)((M + rowdot_bn(ct) - 1) / rowdot_bn(ct));
+        size_t o = 0;
+        c_off = o;
+        o += al(e * (size_t)Mp * (size_t)Bp);
+        u_off = o;
+        o += al(e * (size_t)Mp * (size_t)Bp);
+        d_off = o;
+        o += al(e * (size_t)Mp * (size_t)Pcp);
+        zr_off = o;
+        o += al(dsz * (size_t)M * (size_t)Pcp);
+        zt_off = o;
+        o += al(dsz * (size_t)M * (size_t)Pcp);
+        er_off = o;
+        o += al(dsz * (size_t)M * (size_t)Pcp);
+        et_off = o;
+        o += al(dsz * (size_t)M * (size_t)Pcp);
+        g_off = o;
+        o += al(e * (size_t)Pcp * (size_t)Bp);
+        gt_off = o;
+        if (ct == CT_BF3) o += al(e * (size_t)Bp * (size_t)Pcp);
+        pc_off = o;
+        o += al(8 * (size_t)S * (size_t)M * (size_t)B);
+        pr_off = o;
+        o += al(8 * (size_t)(2 * T) * 2 * (size_t)Pc);
+        total = o;
+    }
+};
+
+int64_t bwd2_chunk_for(int64_t M, int64_t P, int64_t B, int ct, size_t ws_bytes)
+{
+    if (Bwd2Layout(M, P, B, ct).total <= ws_bytes) return P;
+    int64_t lo = 0, hi = pad_up(P) / kPad;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (Bwd2Layout(M, mid * kPad, B, ct).total <= ws_bytes)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return std::min<int64_t>(lo * kPad, P);
+}
+
+} // namespace
+
+extern "C" {
+
+zp_status zp_series_bwd2_workspace(int64_t M, int64_t P, int64_t B, int32_t prec, size_t *full_bytes,
+                                   size_t *min_bytes)
+{
+    if (!full_bytes || M < 0 || P < 0 || B < 0) return set_error(ZP_ERR_ARG, "bad argument");
+    if (prec < ZP_FP64 || prec > ZP_BF16X3) return set_error(ZP_ERR_PREC, "unknown prec");
+    const int ct = ct_of(prec);
+    const int64_t P1 = std::min<int64_t>(P, kPad);
+    *full_bytes = std::max({Bwd2Layout(M, P, B, ct).total, JvpLayout(M, P, B, ct).total, (size_t)256});
+    if (min_bytes) *min_bytes = std::max({Bwd2Layout(M, P1, B, ct).total, JvpLayout(M, P1, B, ct).total, (size_t)256});
+    return ZP_OK;
+}
+
+zp_status zp_series_bwd2(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r, const double *d_theta,
+                         int64_t P, const double *d_c, int64_t B, int32_t prec, const double *d_g, const double *d_uc,
+                         const double *d_ur, const double *d_ut, double *d_out_g, double *d_out_c, double *d_out_r,
+                         double *d_out_t, void *d_ws, size_t ws_bytes, void *stream)
+{
+    zp_status st = common_checks(h_n, h_m, M, P, B, prec);
+    if (st != ZP_OK) return st;
+    if (P == 0 || B == 0 || M == 0) return ZP_OK;
+    if (!d_r || !d_theta || !d_c || !d_g) return set_error(ZP_ERR_ARG, "null pointer");
+    if (!d_out_g && !d_out_c && !d_out_r && !d_out_t) return ZP_OK;
+    if (!d_ws || ((uintptr_t)d_ws & 255)) return set_error(ZP_ERR_ARG, "workspace must be non-null and 256-byte aligned");
+    const int ct = ct_of(prec);
+    const int64_t Pc = bwd2_chunk_for(M, P, B, ct, ws_bytes);
+    if (Pc <= 0 || ws_bytes < JvpLayout(M, std::min<int64_t>(P, kPad), B, ct).total)
+        return set_error(ZP_ERR_WORKSPACE, "workspace smaller than the minimum (zp_series_bwd2_workspace)");
+    hipStream_t s = (hipStream_t)stream;
+    std::shared_ptr<Plan> plan;
+    st = get_plan(h_n, h_m, M, &plan);
+    if (st != ZP_OK) return st;
+
+    const bool need_u = d_uc != nullptr;                  // terms with uc
+    const bool need_dir = d_ur != nullptr || d_ut != nullptr; // terms with ur, ut
+    const bool want_rt = d_out_r || d_out_t;
+    const bool run_c = d_out_c && need_dir;
+    const bool run_u = want_rt && need_u;   // row-dot against g uc^T with dZ/dr, dZ/dtheta
+    const bool run_e = want_rt && need_dir; // row-dot against g c^T with Er, Et
+    if (d_out_c && !need_dir) {
+        st = launch_zero_pad(d_out_c, CT_F64, 0, 0, M, B, 0, s);
+        if (st != ZP_OK) return st;
+    }
+    const Bwd2Layout L(M, Pc, B, ct);
+    char *ws = (char *)d_ws;
+    const int64_t Mp = L.Mp, Bp = L.Bp;
+    if (run_e) {
+        st = launch_convert(d_c, M, B, B, ct, ws + L.c_off, Bp, Mp, Mp * Bp, false, s);
+        if (st != ZP_OK) return st;
+    }
+    if (run_u) {
+        st = launch_convert(d_uc, M, B, B, ct, ws + L.u_off, Bp, Mp, Mp * Bp, false, s);
+        if (st != ZP_OK) return st;
+    }
+    const int zfmt = ct == CT_F64 ? F64 : ct == CT_F32 ? F32 : B16X3;
+    const int dfmt = ct == CT_F64 ? F64 : F32;
+    const int BN = rowdot_bn(ct);
+    for (int64_t p0 = 0; p0 < P; p0 += Pc) {
+        const int64_t pc = std::min(Pc, P - p0);
+        const int64_t pcp = pad_up(pc);
+        if (!run_c && !run_u && !run_e) { // the r / theta outputs of this chunk are zero
+            if (d_out_r) st = launch_zero_pad(d_out_r + p0, CT_F64, 0, 0, 1, pc, 0, s);
+            if (st == ZP_OK && d_out_t) st = launch_zero_pad(d_out_t + p0, CT_F64, 0, 0, 1, pc, 0, s);
+            if (st != ZP_OK) return st;
+            continue;
+        }
+        // basis-derived planes of the chunk
+        Planes o{};
+        o.ld = pcp;
+        o.sub = Mp * pcp;
+        if (run_u) {
+            o.plane[1] = ws + L.zr_off;
+            o.fmt[1] = dfmt;
+            o.plane[4] = ws + L.zt_off;
+            o.fmt[4] = dfmt;
+        }
+        if (run_c) {
+            st = launch_zero_pad(ws + L.d_off, ct, M, pc, Mp, pcp, Mp * pcp, s);
+            if (st != ZP_OK) return st;
+            o.dir = ws + L.d_off;
+            o.dir_fmt = zfmt;
+        }
+        if (run_e) {
+            o.sec_r = ws + L.er_off;
+            o.sec_t = ws + L.et_off;
+            o.sec_fmt = dfmt;
+        }
+        if (run_c || run_e) {
+            o.dir_r = d_ur ? d_ur + p0 : nullptr;
+            o.dir_th = d_ut ? d_ut + p0 : nullptr;
+        }
+        st = launch_chain_kernel(*plan, d_r + p0, d_theta + p0, pc, run_e ? 2 : 1, true, o, s);
+        if (st != ZP_OK) return st;
+        // the chunk's g: [pcp][Bp] (and [Bp][pcp] for the bf16 dL/dc operand)
+        void *gbuf = ws + L.g_off;
+        st = launch_convert(d_g + p0 * B, pc, B, B, ct, gbuf, Bp, pcp, pcp * Bp, false, s);
+        if (st != ZP_OK) return st;
+        if (run_c) {
+            if (ct == CT_BF3) {
+                st = launch_convert(d_g + p0 * B, pc, B, B, ct, ws + L.gt_off, pcp, Bp, Bp * pcp, true, s);
+                if (st != ZP_OK) return st;
+            }
+            GemmDesc g{};
+            g.ct = ct;
+            g.a = Operand{ws + L.d_off, pcp, Mp * pcp, LAY_KC}; // A(i=q, k=p) = D[q][p]
+            if (ct == CT_BF3)
+                g.b = Operand{ws + L.gt_off, pcp, Bp * pcp, LAY_KC};
+            else
+                g.b = Operand{gbuf, Bp, pcp * Bp, LAY_XC};
+            g.M = M;
+            g.N = B;
+            g.K = pcp;
+            g.splits = splits_for(M, B, pcp, ct);
+            g.epi = EPI_PARTIAL;
+            g.C = (double *)(ws + L.pc_off);
+            g.ldc = B;
+            st = launch_gemm(g, s);
+            if (st != ZP_OK) return st;
+            st = launch_splitk_reduce(g.C, g.splits, M, B, d_out_c, B, p0 > 0, s);
+            if (st != ZP_OK) return st;
+        }
+        if (run_u || run_e) {
+            double *part = (double *)(ws + L.pr_off);
+            int tiles = 0;
+            for (int which = 0; which < 2; ++which) {
+                if (which == 0 ? !run_u : !run_e) continue;
+                GemmDesc g{};
+                g.ct = ct;
+                g.a = Operand{gbuf, Bp, pcp * Bp, LAY_KC}; // A(i=p, k=b) = g[p][b]
+                g.b = Operand{ws + (which == 0 ? L.u_off : L.c_off), Bp, Mp * Bp, LAY_KC};
+                g.M = pc;
+                g.N = M;
+                g.K = Bp;
+                g.splits = 1;
+                g.epi = EPI_ROWDOT;
+                g.D1 = ws + (which == 0 ? L.zr_off : L.er_off);
+                g.D2 = ws + (which == 0 ? L.zt_off : L.et_off);
+                g.ldd = pcp;
+                g.d_f32 = ct != CT_F64;
+                g.part = part + (size_t)tiles * 2 * (size_t)pc;
+                st = launch_gemm(g, s);
+                if (st != ZP_OK) return st;
+                tiles += (int)((M + BN - 1) / BN);
+            }
+            st = launch_rowdot_reduce(part, tiles, pc, d_out_r ? d_out_r + p0 : nullptr,
+                                      d_out_t ? d_out_t + p0 : nullptr, s);
+            if (st != ZP_OK) return st;
+        }
+    }
+    if (d_out_g) // Z^T uc + (ur dZ/dr + ut dZ/dtheta)^T c
+        return zp_series_jvp(h_n, h_m, M, d_r, d_theta, P, d_c, B, prec, d_uc, d_ur, d_ut, d_out_g, d_ws, ws_bytes,
+                             stream);
+    return ZP_OK;
+}
+
+} // extern "C"

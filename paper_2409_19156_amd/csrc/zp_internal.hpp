@@ -127,6 +127,11 @@ enum PlaneFmt : int32_t { F64 = 0, F32 = 1, B16X3 = 2 };
 // of the basis along per-point tangents (dr, dtheta; either may be null),
 // in format dir_fmt with the planes' ld and sub; kb_dir, if not null, gets its
 // k-blocked bf16 copy (like kb).
+// sec_r / sec_t, if not null (with J = 2 and the basis), receive the
+// derivatives of that directional derivative along r and theta:
+//   sec_r = dr[p] d2Z/dr2 + dtheta[p] d2Z/(dr dtheta)
+//   sec_t = dr[p] d2Z/(dr dtheta) + dtheta[p] d2Z/dtheta2
+// in format sec_fmt with the planes' ld and sub.
 struct Planes {
     void *plane[5];
     int64_t ld;
@@ -140,6 +145,9 @@ struct Planes {
     const double *dir_r;
     const double *dir_th;
     void *kb_dir;
+    void *sec_r;
+    void *sec_t;
+    int32_t sec_fmt;
 };
 
 // Launch the chain kernel: radial only (angular = false) or basis.  J is the

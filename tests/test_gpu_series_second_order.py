@@ -1,0 +1,156 @@
+"""GPU parity of the second-order adjoint of the series (zp_series_bwd2:
+double backward / Hessian-vector products) against the oracle's term-by-term
+formula, and torch's double-backward checks through ZernikeSeries.
+
+Error measure: ||GPU - oracle||_inf / ||oracle||_inf per output tensor; 1e-12
+for FP64, 1e-6 for the FP32 and split-BF16x3 contractions.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import zp_workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16x3": 1e-6}
+NAMES = ("out_g", "out_c", "out_r", "out_t")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def zp():
+    import paper_2409_19156_amd as zp
+
+    assert torch.cuda.is_available()
+    return zp
+
+
+def _dev(x):
+    return None if x is None else torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def _rel(got, ref):
+    got, ref = np.asarray(got), np.asarray(ref)
+    assert got.shape == ref.shape
+    assert np.all(np.isfinite(got))
+    return float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+def _case(nmax, npts, nb, seed):
+    rng = np.random.default_rng(seed)
+    n, m = W.ansi_modes(nmax)
+    r, th = W.disc_points(seed, npts)
+    c = rng.standard_normal((n.size, nb)) / (n + 1.0)[:, None]
+    g = rng.standard_normal((npts, nb))
+    uc = rng.standard_normal((n.size, nb))
+    ur, ut = rng.standard_normal(npts), rng.standard_normal(npts)
+    return n, m, r, th, c, g, uc, ur, ut
+
+
+def _oracle(o, n, m, r, th, c, g, uc, ur, ut):
+    Z, Zr, Zt = o.series_basis(n, m, r, th)
+    zero = np.zeros
+    uc = zero(c.shape) if uc is None else uc
+    ur = zero(r.size) if ur is None else ur
+    ut = zero(r.size) if ut is None else ut
+    return o.series_bwd2(Z, Zr, Zt, *o.series_basis2(n, m, r, th), c, g, uc, ur, ut)
+
+
+def _gpu(zp, n, m, r, th, c, g, uc, ur, ut, prec, ws=None):
+    outs = zp.series_backward2(n, m, _dev(r), _dev(th), _dev(c), _dev(g), _dev(uc), _dev(ur), _dev(ut), prec, ws=ws)
+    torch.cuda.synchronize()
+    return [x.cpu().numpy() for x in outs]
+
+
+@pytest.fixture(scope="module")
+def case12(oracle_mod):
+    args = _case(12, 700, 3, seed=31)
+    return args, _oracle(oracle_mod, *args)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_bwd2_matches_oracle(zp, case12, prec):
+    args, ref = case12
+    got = _gpu(zp, *args, prec)
+    errs = {k: _rel(a, b) for k, a, b in zip(NAMES, got, ref)}
+    _say(f"bwd2 n<=12 P=700 B=3 {prec}:", {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, e in errs.items():
+        assert e <= TOL[prec], (k, e)
+
+
+@pytest.mark.parametrize("which", ["uc", "ur", "ut", "none"])
+def test_bwd2_partial_cotangents(zp, oracle_mod, which):
+    n, m, r, th, c, g, uc, ur, ut = _case(9, 300, 2, seed=32)
+    keep = {"uc": (uc, None, None), "ur": (None, ur, None), "ut": (None, None, ut), "none": (None, None, None)}[which]
+    ref = _oracle(oracle_mod, n, m, r, th, c, g, *keep)
+    got = _gpu(zp, n, m, r, th, c, g, *keep, "fp64")
+    for k, a, b in zip(NAMES, got, ref):
+        if not np.any(b):
+            assert not np.any(a), (which, k)
+        else:
+            assert _rel(a, b) <= 1e-12, (which, k)
+
+
+def test_bwd2_chunked_workspace(zp, case12):
+    import ctypes
+
+    from paper_2409_19156_amd import _lib
+
+    args, ref = case12
+    n = args[0]
+    full, mn = ctypes.c_size_t(), ctypes.c_size_t()
+    assert _lib.load().zp_series_bwd2_workspace(n.size, 700, 3, 0, ctypes.byref(full), ctypes.byref(mn)) == 0
+    assert mn.value < full.value
+    ws = torch.empty(mn.value, dtype=torch.uint8, device="cuda")
+    got = _gpu(zp, *args, "fp64", ws=ws)
+    for k, a, b in zip(NAMES, got, ref):
+        assert _rel(a, b) <= 1e-12, k
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_bwd2_n40(zp, oracle_mod, prec):
+    """861 modes, 4096 points, 64 sets."""
+    args = _case(40, 4096, 64, seed=33)
+    ref = _oracle(oracle_mod, *args)
+    got = _gpu(zp, *args, prec)
+    errs = {k: _rel(a, b) for k, a, b in zip(NAMES, got, ref)}
+    _say(f"bwd2 n<=40 P=4096 B=64 {prec}:", {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, e in errs.items():
+        assert e <= TOL[prec], (k, e)
+
+
+def test_double_backward_gradgradcheck(zp):
+    n, m = W.ansi_modes(5)
+    rng = np.random.default_rng(34)
+    r, th = W.disc_points(35, 6)
+    r = _dev(0.1 + 0.8 * r).requires_grad_()
+    th = _dev(th).requires_grad_()
+    c = _dev(rng.standard_normal((n.size, 2))).requires_grad_()
+    fn = lambda c_, r_, t_: zp.series(c_, r_, t_, n, m, "fp64")  # noqa: E731
+    assert torch.autograd.gradgradcheck(fn, (c, r, th), eps=1e-6, atol=1e-7, rtol=1e-5)
+
+
+def test_hessian_vector_product_matches_oracle(zp, oracle_mod):
+    """Hv of L = sum(w * f) through autograd's double backward (which calls
+    zp_series_bwd2) against the oracle formula: with g = w fixed, the gradient
+    (grad_c, grad_r, grad_t) has the directional derivative along
+    (vc, vr, vt) given by series_bwd2 with cotangents (vc, vr, vt)."""
+    n, m, r, th, c, w, vc, vr, vt = _case(10, 257, 2, seed=36)
+    rt, tt, ct = (_dev(x).requires_grad_() for x in (r, th, c))
+    f = zp.series(ct, rt, tt, n, m, "fp64")
+    L = (f * _dev(w)).sum()
+    gc, gr, gt = torch.autograd.grad(L, (ct, rt, tt), create_graph=True)
+    s = (gc * _dev(vc)).sum() + (gr * _dev(vr)).sum() + (gt * _dev(vt)).sum()
+    hc, hr, ht = torch.autograd.grad(s, (ct, rt, tt))
+    _, oc, orr, ot = _oracle(oracle_mod, n, m, r, th, c, w, vc, vr, vt)
+    for got, ref in ((hc, oc), (hr, orr), (ht, ot)):
+        assert _rel(got.cpu().numpy(), ref) <= 1e-12
