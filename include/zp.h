@@ -118,6 +118,18 @@ zp_status zp_radial_direct(const int32_t *h_n, const int32_t *h_m, int64_t M, co
                            int32_t max_dr, double *d_out, void *stream);
 
 /*
+ * zp_radial_zernike_recursion -- the same outputs as zp_radial, by the
+ * Zernike recursion Eq. (zernike-recursion), R_n^m = r (R_{n-1}^{|m-1|} +
+ * R_{n-1}^{m+1}) - R_{n-2}^m, over the whole (n, |m|) triangle up to the
+ * largest requested n, with out-of-range terms zero; derivatives by
+ * differentiating the recursion.  A second comparator for the paper's
+ * accuracy study (Sec. 2 and 4), for n <= 60 only.  Arguments and errors as
+ * zp_radial; ZP_ERR_ARG also for n > 60.
+ */
+zp_status zp_radial_zernike_recursion(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r, int64_t P,
+                                      int32_t max_dr, double *d_out, void *stream);
+
+/*
  * Zernike series f(r_p, theta_p)_b = sum_k c[k][b] Z_k(r_p, theta_p) for B
  * coefficient sets at once (the basis contracted with coefficients; the
  * paper's use of Zernike polynomials as a spectral basis, Sec. 1 and 3), and

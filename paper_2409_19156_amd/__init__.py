@@ -17,7 +17,7 @@ from ._lib import ZpError
 Z, DR, DR2, DR3, DTHETA = 1, 2, 4, 8, 16
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
-__all__ = ["radial", "radial_direct", "basis", "ZpError", "Z", "DR", "DR2", "DR3", "DTHETA", "PREC", "modes_i32"]
+__all__ = ["radial", "radial_direct", "radial_zernike_recursion", "basis", "ZpError", "Z", "DR", "DR2", "DR3", "DTHETA", "PREC", "modes_i32"]
 
 
 def modes_i32(n, m):
@@ -78,6 +78,22 @@ def radial_direct(n, m, r: torch.Tensor, max_dr: int = 0) -> torch.Tensor:
         st = lib.zp_radial_direct(nh.ctypes.data, mh.ctypes.data, M, r.data_ptr(), P, int(max_dr), out.data_ptr(),
                                   _stream(r.device))
     _lib.check(st, "zp_radial_direct")
+    return out
+
+
+def radial_zernike_recursion(n, m, r: torch.Tensor, max_dr: int = 0) -> torch.Tensor:
+    """Same outputs as ``radial`` by the Zernike recursion (Eq.
+    zernike-recursion) over the whole (n, |m|) triangle; n <= 60.  For accuracy
+    comparisons only."""
+    lib = _lib.load()
+    nh, mh = modes_i32(n, m)
+    r = _points(r, "r")
+    M, P = nh.size, r.numel()
+    out = torch.empty((max_dr + 1, M, P), dtype=torch.float64, device=r.device)
+    with torch.cuda.device(r.device):
+        st = lib.zp_radial_zernike_recursion(nh.ctypes.data, mh.ctypes.data, M, r.data_ptr(), P, int(max_dr),
+                                             out.data_ptr(), _stream(r.device))
+    _lib.check(st, "zp_radial_zernike_recursion")
     return out
 
 

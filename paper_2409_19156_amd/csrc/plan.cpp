@@ -170,8 +170,51 @@ zp_status get_direct_table(Plan &plan)
     return plan.direct_status == ZP_OK ? ZP_OK : set_error(plan.direct_status, "direct table upload failed");
 }
 
+zp_status get_zrec_table(Plan &plan)
+{
+    std::call_once(plan.zrec_once, [&plan] {
+        const int nmax = plan.nmax;
+        // triangle entry of (n, alpha): rows k < n hold k/2 + 1 entries each
+        auto entry = [](int n, int a) {
+            int t = 0;
+            for (int k = 0; k < n; ++k) t += k / 2 + 1;
+            return t + (a - (n & 1)) / 2;
+        };
+        const int T = entry(nmax + 1, (nmax + 1) & 1);
+        std::vector<int32_t> cnt((size_t)T + 1, 0), cols(plan.n.size());
+        for (size_t i = 0; i < plan.n.size(); ++i) ++cnt[(size_t)entry(plan.n[i], std::abs(plan.m[i])) + 1];
+        for (int t = 0; t < T; ++t) cnt[(size_t)t + 1] += cnt[(size_t)t];
+        std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+        for (size_t i = 0; i < plan.n.size(); ++i) // caller's order within an entry
+            cols[(size_t)fill[(size_t)entry(plan.n[i], std::abs(plan.m[i]))]++] = (int32_t)i;
+        const size_t a = cnt.size() * sizeof(int32_t), a_al = (a + 255) / 256 * 256;
+        const size_t total = a_al + cols.size() * sizeof(int32_t);
+        std::vector<unsigned char> host(total, 0);
+        std::copy_n((const unsigned char *)cnt.data(), a, host.data());
+        std::copy_n((const unsigned char *)cols.data(), cols.size() * sizeof(int32_t), host.data() + a_al);
+        void *d = nullptr;
+        zp_status st = hip_check(hipMalloc(&d, total), "hipMalloc(recursion table)");
+        if (st == ZP_OK) st = hip_check(hipMemcpy(d, host.data(), total, hipMemcpyHostToDevice), "hipMemcpy(recursion table)");
+        plan.zrec_status = st;
+        if (st == ZP_OK) {
+            plan.d_zrec = d;
+            plan.d_zrec_off = (const int32_t *)d;
+            plan.d_zrec_cols = (const int32_t *)((unsigned char *)d + a_al);
+        }
+    });
+    return plan.zrec_status == ZP_OK ? ZP_OK : set_error(plan.zrec_status, "recursion table upload failed");
+}
+
 Plan::~Plan()
 {
+    if (d_zrec) {
+        int cur = -1;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(device);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(d_zrec);
+        if (cur >= 0) (void)hipSetDevice(cur);
+    }
     if (d_direct) {
         int cur = -1;
         (void)hipGetDevice(&cur);

@@ -112,6 +112,25 @@ zp_status zp_radial_direct(const int32_t *h_n, const int32_t *h_m, int64_t M, co
     return launch_direct_kernel(*plan, d_r, P, max_dr, d_out, (hipStream_t)stream);
 }
 
+zp_status zp_radial_zernike_recursion(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r, int64_t P,
+                                      int32_t max_dr, double *d_out, void *stream)
+{
+    zp_status st = check_modes_arg(h_n, h_m, M);
+    if (st != ZP_OK) return st;
+    if (max_dr < 0 || max_dr > 3) return set_error(ZP_ERR_ORDER, "max_dr must be 0..3");
+    if (P < 0) return set_error(ZP_ERR_ARG, "P < 0");
+    for (int64_t i = 0; i < M; ++i)
+        if (h_n[i] > kZrecNmax) return set_error(ZP_ERR_ARG, "the Zernike-recursion comparator takes n <= 60");
+    if (M == 0 || P == 0) return ZP_OK;
+    if (!d_r || !d_out) return set_error(ZP_ERR_ARG, "null point or output pointer");
+    std::shared_ptr<Plan> plan;
+    st = get_plan(h_n, h_m, M, &plan);
+    if (st != ZP_OK) return st;
+    st = get_zrec_table(*plan);
+    if (st != ZP_OK) return st;
+    return launch_zrec_kernel(*plan, d_r, P, max_dr, d_out, (hipStream_t)stream);
+}
+
 const char *zp_status_string(zp_status s)
 {
     switch (s) {

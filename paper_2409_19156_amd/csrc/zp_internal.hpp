@@ -89,8 +89,23 @@ struct Plan {
     const int64_t *d_direct_off = nullptr; // per mode: offset of its 4 (K+1) coefficients
     const int32_t *d_direct_n = nullptr, *d_direct_m = nullptr;
     const double *d_direct_coef = nullptr;
+    // Column table of the Zernike-recursion comparator, built on first use:
+    // for every (n, alpha) of the triangle n <= nmax in row order (alpha =
+    // n%2, n%2+2, ..., n), the output columns of the requested modes with
+    // that (n, |m|): zrec_off [entries+1] into zrec_cols [M].
+    std::once_flag zrec_once;
+    zp_status zrec_status = ZP_OK;
+    void *d_zrec = nullptr;
+    const int32_t *d_zrec_off = nullptr, *d_zrec_cols = nullptr;
     ~Plan();
 };
+
+// Device table for zp_radial_zernike_recursion (uploaded once per plan).
+zp_status get_zrec_table(Plan &plan);
+
+// Zernike-recursion evaluation (Eq. zernike-recursion): out[j][i][p], j <= J.
+constexpr int kZrecNmax = 60;
+zp_status launch_zrec_kernel(const Plan &plan, const double *d_r, int64_t P, int J, double *out, hipStream_t s);
 
 // Device table for zp_radial_direct (uploaded once per plan).
 zp_status get_direct_table(Plan &plan);

@@ -57,6 +57,7 @@ def test_invalid_modes(lib, n, m):
     assert lib.zp_radial(n.ctypes.data, m.ctypes.data, n.size, FAKE, 4, 0, FAKE, None) == ERR_MODE
     assert b"violates" in lib.zp_last_error()
     assert lib.zp_radial_direct(n.ctypes.data, m.ctypes.data, n.size, FAKE, 4, 0, FAKE, None) == ERR_MODE
+    assert lib.zp_radial_zernike_recursion(n.ctypes.data, m.ctypes.data, n.size, FAKE, 4, 0, FAKE, None) == ERR_MODE
     assert lib.zp_basis(n.ctypes.data, m.ctypes.data, n.size, FAKE, FAKE, 4, 1, FAKE, None) == ERR_MODE
     assert lib.zp_series_fwd(n.ctypes.data, m.ctypes.data, n.size, FAKE, FAKE, 4, FAKE, 2, 0, FAKE, None, FAKE,
                              1 << 20, None) == ERR_MODE
@@ -72,6 +73,10 @@ def test_order_mask_prec_and_sizes(lib):
     for bad in (-1, 4, 7):
         assert lib.zp_radial(nd, md, 2, FAKE, 4, bad, FAKE, None) == ERR_ORDER
         assert lib.zp_radial_direct(nd, md, 2, FAKE, 4, bad, FAKE, None) == ERR_ORDER
+        assert lib.zp_radial_zernike_recursion(nd, md, 2, FAKE, 4, bad, FAKE, None) == ERR_ORDER
+    big, bm = _modes([61, 2], [1, 0])
+    assert lib.zp_radial_zernike_recursion(big.ctypes.data, bm.ctypes.data, 2, FAKE, 4, 0, FAKE, None) == ERR_ARG
+    assert b"n <= 60" in lib.zp_last_error()
     for mask in (0, 32, 33):
         assert lib.zp_basis(nd, md, 2, FAKE, FAKE, 4, mask, FAKE, None) == ERR_ARG
     assert lib.zp_radial(nd, md, -1, FAKE, 4, 0, FAKE, None) == ERR_ARG

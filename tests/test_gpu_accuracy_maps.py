@@ -1,8 +1,9 @@
 """Accuracy maps of the paper's accuracy study (Sec. 4, first figure): every
 radial pair with 0 <= m <= n <= 50 at 100 linearly spaced r in [0, 1], orders
 0..3, per-mode error = max over points of |computed - exact|, for the Jacobi
-recurrence (zp_radial) and for direct FP64 evaluation of the closed form
-(zp_radial_direct), both against the quad-precision oracle.
+recurrence (zp_radial), for direct FP64 evaluation of the closed form
+(zp_radial_direct) and for the Zernike recursion (zp_radial_zernike_recursion),
+all against the quad-precision oracle.
 
 The paper's qualitative findings, checked here: the recurrence stays accurate
 (its stated maximum for n <= 50 is 2.05e-14), direct evaluation degrades with
@@ -36,24 +37,27 @@ def maps(oracle_mod):
     ref = oracle_mod.radial(n, m, r, 3)
     rec = zp.radial(n, m, rd, 3).cpu().numpy()
     direct = zp.radial_direct(n, m, rd, 3).cpu().numpy()
+    zrec = zp.radial_zernike_recursion(n, m, rd, 3).cpu().numpy()
     e_rec = np.abs(rec - ref).max(axis=2)      # [4, modes]
     e_dir = np.abs(direct - ref).max(axis=2)
+    e_zr = np.abs(zrec - ref).max(axis=2)
     for j in range(4):
         print(f"order {j}: recurrence max {e_rec[j].max():.3g} mean {e_rec[j].mean():.3g} | "
-              f"direct max {e_dir[j].max():.3g} mean {e_dir[j].mean():.3g}", flush=True)
+              f"direct max {e_dir[j].max():.3g} mean {e_dir[j].mean():.3g} | "
+              f"Zernike recursion max {e_zr[j].max():.3g} mean {e_zr[j].mean():.3g}", flush=True)
     sys.stdout.flush()
-    return n, m, e_rec, e_dir
+    return n, m, e_rec, e_dir, e_zr
 
 
 def test_recurrence_within_papers_stated_error(maps):
-    n, m, e_rec, _ = maps
+    n, m, e_rec, _, _ = maps
     assert e_rec[0].max() <= 2.05e-14
     for j in range(4):
         assert np.all(e_rec[j] <= 1e-13 * (n + 1.0) ** (2 * j))
 
 
 def test_direct_evaluation_degrades_as_the_paper_reports(maps):
-    n, m, e_rec, e_dir = maps
+    n, m, e_rec, e_dir, _ = maps
     k = int(np.argmax(e_dir[0]))
     assert n[k] >= 49 and m[k] <= 6, (n[k], m[k])
     k50 = int(np.flatnonzero((n == 50) & (m == 0))[0])
@@ -64,3 +68,31 @@ def test_direct_evaluation_degrades_as_the_paper_reports(maps):
     # orders of magnitude worse than the recurrence at high n - m
     hi = (n - m) >= 40
     assert e_dir[0][hi].min() > 100 * e_rec[0][hi].max()
+
+
+def test_zernike_recursion_comparator(maps):
+    """The Zernike recursion (Eq. zernike-recursion) stays accurate at n <= 50
+    (its steps combine neighbours with weights r <= 1): within the basis
+    tolerance, and orders of magnitude better than the direct form where
+    n - m is large."""
+    n, m, _, e_dir, e_zr = maps
+    for j in range(4):
+        assert np.all(e_zr[j] <= 1e-13 * (n + 1.0) ** (2 * j)), j
+    hi = (n - m) >= 40
+    assert e_dir[0][hi].min() > 100 * e_zr[0][hi].max()
+
+
+def test_zernike_recursion_mode_lists(oracle_mod):
+    """Unsorted, duplicated and negative-m modes, ragged P: every column as
+    the oracle gives it."""
+    import paper_2409_19156_amd as zp
+
+    n = np.array([7, 0, 60, 7, 12, 60, 1, 33], dtype=np.int32)
+    m = np.array([-3, 0, 0, 3, 12, -58, -1, 5], dtype=np.int32)
+    for P in (1, 31, 33, 65, 1000):
+        r = np.random.default_rng(P).random(P)
+        ref = oracle_mod.radial(n, m, r, 2)
+        got = zp.radial_zernike_recursion(n, m, torch.from_numpy(r).cuda(), 2).cpu().numpy()
+        for j in range(3):
+            tol = 1e-13 * (n + 1.0) ** (2 * j)
+            assert np.all(np.abs(got[j] - ref[j]).max(axis=1) <= tol), (P, j)
