@@ -6,8 +6,8 @@
 // dimension a multiple of kPad), so tile loads need no bounds checks; stores
 // are masked to the true output size.  Each operand tile is copied into LDS
 // in its global layout (k-contiguous rows, or rows along the other index),
-// with padding chosen so that the MFMA fragment reads are free of bank
-// conflicts; the fragment reads follow the layout.  The bf16 path needs
+// with a row swizzle or padding that keeps the MFMA fragment reads and the
+// tile stores free of bank conflicts; the fragment reads follow the layout.  The bf16 path needs
 // eight consecutive k per lane, so an operand that is not k-contiguous in
 // memory is transposed while it is written to LDS.  Tiles are double
 // buffered: the next tile's global loads are in flight during the current
@@ -47,26 +47,46 @@ constexpr int kFlush = 128;
 template <int CT> struct CTr;
 template <> struct CTr<CT_F64> {
     using T = double;
-    static constexpr int NP = 1, PK = 2;
+    static constexpr int NP = 1;
 };
 template <> struct CTr<CT_F32> {
     using T = float;
-    static constexpr int NP = 1, PK = 4;
+    static constexpr int NP = 1;
 };
 template <> struct CTr<CT_BF3> {
     using T = uint16_t;
-    static constexpr int NP = 3, PK = 8;
+    static constexpr int NP = 3;
 };
 
 // LDS geometry and global->LDS copy of one operand tile (X rows of the output
-// index by BK).  LDS holds the tile either as [X][BK+PK] (k contiguous: the
+// index by BK).  LDS holds the tile either as [X][BK] rows (k contiguous: the
 // k-contiguous and k-blocked layouts, and every bf16 operand) or as
-// [BK][X+16] (x contiguous).  Pads keep the fragment reads conflict-free.
+// [BK][X+16] (x contiguous, the pad keeping the fragment reads conflict-free).
+//
+// Rows along x are stored unpadded with the k index XOR-swizzled by the row:
+// element (x, k) sits at x*BK + (k ^ swz(x)).  swz(x) is a multiple of the
+// 16-byte store width, so each global vector lands contiguously, and it
+// spreads the rows over the 64 LDS banks:
+//   FP64 : swz = x & 14         (8-byte elements, 128-byte rows)
+//   FP32 : swz = (x & 14) * 2   (4-byte elements, 128-byte rows)
+//   bf16 : swz = ((x>>2) & 3)*8 (16-byte k blocks, 64-byte rows)
+// With it, the sixteen lanes that read rows x..x+15 of one k (x4 shapes: two
+// k per 32-lane half; bf16: one 16-byte block) and the lanes of one store
+// quarter all touch distinct banks.
+template <int CT> __device__ __forceinline__ constexpr int row_swizzle(int x)
+{
+    return CT == CT_F64 ? (x & 14) : CT == CT_F32 ? ((x & 14) << 1) : (((x >> 2) & 3) << 3);
+}
+
 template <int CT, int X, int BK, int LAY> struct Tile {
     using T = typename CTr<CT>::T;
     static constexpr bool ROWS_X = LAY != LAY_XC || CT == CT_BF3;
-    static constexpr int STRIDE = ROWS_X ? BK + CTr<CT>::PK : X + 16;
+    static constexpr int STRIDE = ROWS_X ? BK : X + 16;
     static constexpr int ELEMS = (ROWS_X ? X : BK) * STRIDE;
+    static_assert(!ROWS_X || BK == (CT == CT_F64 ? 16 : 32), "row swizzle assumes 128- or 64-byte rows");
+
+    // LDS position of element (x, k) of a row-major (ROWS_X) tile
+    static __device__ __forceinline__ int at(int x, int k) { return x * BK + (k ^ row_swizzle<CT>(x)); }
     static constexpr int VEC = 16 / (int)sizeof(T);
     // global tile as GROWS rows of GCOLS contiguous elements
     static constexpr int GROWS = LAY == LAY_KC ? X : LAY == LAY_XC ? BK : BK / VEC;
@@ -115,15 +135,17 @@ template <int CT, int X, int BK, int LAY> struct Tile {
 #pragma unroll
             for (int p = 0; p < CTr<CT>::NP; ++p) {
                 T *L = lds + p * ELEMS;
-                if (LAY == LAY_KC || !ROWS_X) {
+                if (!ROWS_X) {
                     *(u4 *)(L + gr * STRIDE + gc) = reg[v][p];
+                } else if (LAY == LAY_KC) {
+                    *(u4 *)(L + at(gr, gc)) = reg[v][p];
                 } else if (LAY == LAY_KB8) {
-                    *(u4 *)(L + (gc / 8) * STRIDE + gr * 8) = reg[v][p];
+                    *(u4 *)(L + at(gc / 8, gr * 8)) = reg[v][p];
                 } else { // bf16 operand contiguous along x: transpose into [x][k]
                     const u4 w = reg[v][p];
 #pragma unroll
                     for (int q = 0; q < VEC; ++q)
-                        L[(gc + q) * STRIDE + gr] = (T)((q & 1) ? (w[q >> 1] >> 16) : (w[q >> 1] & 0xFFFFu));
+                        L[at(gc + q, gr)] = (T)((q & 1) ? (w[q >> 1] >> 16) : (w[q >> 1] & 0xFFFFu));
                 }
             }
         }
@@ -134,7 +156,7 @@ template <int CT, int X, int BK, int LAY> struct Tile {
 template <class TL>
 __device__ __forceinline__ typename TL::T frag1(const typename TL::T *L, int x, int k)
 {
-    return TL::ROWS_X ? L[x * TL::STRIDE + k] : L[k * TL::STRIDE + x];
+    return TL::ROWS_X ? L[TL::at(x, k)] : L[k * TL::STRIDE + x];
 }
 
 // Tile configuration per element type: BM x BN workgroup tile of eight
@@ -264,13 +286,13 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc g)
                 for (int a = 0; a < FM; ++a)
 #pragma unroll
                     for (int p = 0; p < 3; ++p)
-                        fa[a][p] = *(const bf8 *)(LA + p * TA::ELEMS + (wm0 + a * 16 + lx) * TA::STRIDE + kk + 8 * lk);
+                        fa[a][p] = *(const bf8 *)(LA + p * TA::ELEMS + TA::at(wm0 + a * 16 + lx, kk + 8 * lk));
 #pragma unroll
                 for (int b = 0; b < FN; ++b) {
                     bf8 fb[3];
 #pragma unroll
                     for (int p = 0; p < 3; ++p)
-                        fb[p] = *(const bf8 *)(LB + p * TB::ELEMS + (wn0 + b * 16 + lx) * TB::STRIDE + kk + 8 * lk);
+                        fb[p] = *(const bf8 *)(LB + p * TB::ELEMS + TB::at(wn0 + b * 16 + lx, kk + 8 * lk));
 #pragma unroll
                     for (int a = 0; a < FM; ++a) {
                         // small cross products first, the leading one last
