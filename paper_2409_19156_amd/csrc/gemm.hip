@@ -197,8 +197,9 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc g)
     // Tile this workgroup computes.  Workgroups are dispatched in linear order
     // and dealt round-robin to the 8 XCDs, each with its own L2.  Give every
     // XCD a contiguous range of logical tiles, and order logical tiles split
-    // (slowest), then row tile, then column tile (fastest): the workgroups that
-    // share an A panel then run together on one XCD and read it from its L2.
+    // (slowest), then row tile, then column tile (fastest; or the two swapped
+    // with g.order = 1): the workgroups that share an A (or B) panel then run
+    // together on one XCD and read it from its L2.
     int bx, by, bz;
     {
         const int64_t nx = gridDim.x, ny = gridDim.y;
@@ -206,8 +207,13 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc g)
         const int64_t id = blockIdx.x + nx * (blockIdx.y + ny * (int64_t)blockIdx.z);
         const int64_t t8 = total / 8 * 8;
         const int64_t lid = id < t8 ? (id % 8) * (t8 / 8) + id / 8 : id;
-        by = (int)(lid % ny);
-        bx = (int)((lid / ny) % nx);
+        if (g.order == 0) {
+            by = (int)(lid % ny);
+            bx = (int)((lid / ny) % nx);
+        } else {
+            bx = (int)(lid % nx);
+            by = (int)((lid / nx) % ny);
+        }
         bz = (int)(lid / (ny * nx));
     }
     const int64_t i0 = (int64_t)bx * BM;
@@ -356,69 +362,55 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc g)
                     if (i < g.M && j < g.N) Cp[i * g.ldc + j] = value(a, b, t);
                 }
             }
-    } else { // EPI_ROWDOT
-        // Each lane holds 16 rows (4 fragments x 4 accumulator elements) of
-        // 16 columns' products h * d; the 16 lanes sharing those rows (lane
-        // bits 0-3) hold the other columns.  A butterfly reduce-scatter over
-        // lane bits 3..0 sums each row across the 16 lanes in 15 exchanges per
-        // output (every lane ends with the total of one row); waves that share
-        // rows are then added in a fixed order through LDS.
-        constexpr int WCOLS = BN / WN;
-        static_assert(FM * 4 == 16, "row-dot epilogue expects 16 rows per lane");
-        __shared__ double red[2][WCOLS][BM];
-        const int wcol = wave / (BM / WM);
+    } else { // EPI_COLDOT
+        // Column j of the tile is spread over the lanes lx + 16*lk (lk = 0..3),
+        // each holding 16 of its rows (4 fragments x 4 accumulator elements).
+        // Each lane forms its 16 products h * d -- sixteen lanes read 16
+        // consecutive j of one plane row, 128 contiguous bytes -- then the four
+        // lanes of a column are summed with two exchanges, and the wave rows
+        // that share the column are added in a fixed order through LDS.
+        constexpr int WROWS = BM / WM;
+        __shared__ double red[2][WROWS][BN];
+        const int wrow = wave % (BM / WM);
         using DT = typename std::conditional<CT == CT_F64, double, float>::type;
         const DT *D1 = (const DT *)g.D1;
         const DT *D2 = (const DT *)g.D2;
-        double v1[16], v2[16];
 #pragma unroll
-        for (int a = 0; a < FM; ++a)
+        for (int b = 0; b < FN; ++b) {
+            const int64_t j = j0 + wn0 + b * 16 + lx;
+            double s1 = 0.0, s2 = 0.0;
+            if (j < g.N) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int64_t i = i0 + wm0 + a * 16 + row_of(t);
-                double s1 = 0.0, s2 = 0.0;
+                for (int a = 0; a < FM; ++a)
 #pragma unroll
-                for (int b = 0; b < FN; ++b) {
-                    const int64_t j = j0 + wn0 + b * 16 + lx;
-                    if (i < g.M && j < g.N) {
-                        const int64_t o = j * g.ldd + i;
-                        const double h = value(a, b, t);
-                        s1 = __builtin_fma(h, (double)D1[o], s1);
-                        s2 = __builtin_fma(h, (double)D2[o], s2);
+                    for (int t = 0; t < 4; ++t) {
+                        const int64_t i = i0 + wm0 + a * 16 + row_of(t);
+                        if (i < g.M) {
+                            const int64_t o = i * g.ldd + j;
+                            const double h = value(a, b, t);
+                            s1 = __builtin_fma(h, (double)D1[o], s1);
+                            s2 = __builtin_fma(h, (double)D2[o], s2);
+                        }
                     }
-                }
-                v1[a * 4 + t] = s1;
-                v2[a * 4 + t] = s2;
             }
-#pragma unroll
-        for (int half = 8; half >= 1; half >>= 1) {
-            const bool upper = (lx & half) != 0;
-#pragma unroll
-            for (int k = 0; k < half; ++k) {
-                const double send1 = upper ? v1[k] : v1[k + half];
-                const double send2 = upper ? v2[k] : v2[k + half];
-                const double keep1 = upper ? v1[k + half] : v1[k];
-                const double keep2 = upper ? v2[k + half] : v2[k];
-                v1[k] = keep1 + __shfl_xor(send1, half);
-                v2[k] = keep2 + __shfl_xor(send2, half);
+            s1 += __shfl_xor(s1, 16);
+            s2 += __shfl_xor(s2, 16);
+            s1 += __shfl_xor(s1, 32);
+            s2 += __shfl_xor(s2, 32);
+            if (lk == 0) {
+                red[0][wrow][wn0 + b * 16 + lx] = s1;
+                red[1][wrow][wn0 + b * 16 + lx] = s2;
             }
-        }
-        // lane lx now holds the row whose 4-bit index (a*4 + t) equals lx
-        {
-            const int r16 = lx;
-            const int il = wm0 + (r16 >> 2) * 16 + row_of(r16 & 3);
-            red[0][wcol][il] = v1[0];
-            red[1][wcol][il] = v2[0];
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < 2 * BM; e += kThreads) {
-            const int o = e / BM, il = e % BM;
-            const int64_t i = i0 + il;
-            if (i >= g.M) continue;
+        for (int e = threadIdx.x; e < 2 * BN; e += kThreads) {
+            const int o = e / BN, jl = e % BN;
+            const int64_t j = j0 + jl;
+            if (j >= g.N) continue;
             double sum = 0.0;
 #pragma unroll
-            for (int c = 0; c < WCOLS; ++c) sum += red[o][c][il];
-            g.part[((int64_t)by * 2 + o) * g.M + i] = sum;
+            for (int r = 0; r < WROWS; ++r) sum += red[o][r][jl];
+            g.part[((int64_t)bx * 2 + o) * g.N + j] = sum;
         }
     }
 }
@@ -463,7 +455,7 @@ hipError_t launch_c(const GemmDesc &g, hipStream_t s)
     switch (g.epi) {
     case EPI_STORE: return launch_e<CT, EPI_STORE>(g, s);
     case EPI_PARTIAL: return launch_e<CT, EPI_PARTIAL>(g, s);
-    default: return launch_e<CT, EPI_ROWDOT>(g, s);
+    default: return launch_e<CT, EPI_COLDOT>(g, s);
     }
 }
 
@@ -591,7 +583,7 @@ __global__ void splitk_reduce_kernel(const double *__restrict__ part, int S, int
     }
 }
 
-__global__ void rowdot_reduce_kernel(const double *__restrict__ part, int T, int64_t P, double *out1, double *out2)
+__global__ void coldot_reduce_kernel(const double *__restrict__ part, int T, int64_t P, double *out1, double *out2)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
@@ -612,9 +604,9 @@ unsigned grid_for(int64_t total, int block)
 
 } // namespace
 
-int rowdot_bn(int ct)
+int coldot_bm(int ct)
 {
-    return ct == CT_F64 ? Cfg<CT_F64>::BN : ct == CT_F32 ? Cfg<CT_F32>::BN : Cfg<CT_BF3>::BN;
+    return ct == CT_F64 ? Cfg<CT_F64>::BM : ct == CT_F32 ? Cfg<CT_F32>::BM : Cfg<CT_BF3>::BM;
 }
 
 zp_status launch_gemm(const GemmDesc &g, hipStream_t s)
@@ -687,11 +679,11 @@ zp_status launch_splitk_reduce(const double *part, int S, int64_t M, int64_t N, 
     return hip_check(hipGetLastError(), "split-K reduce launch");
 }
 
-zp_status launch_rowdot_reduce(const double *part, int T, int64_t P, double *out1, double *out2, hipStream_t s)
+zp_status launch_coldot_reduce(const double *part, int T, int64_t P, double *out1, double *out2, hipStream_t s)
 {
-    hipLaunchKernelGGL(rowdot_reduce_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, part, T, P, out1,
+    hipLaunchKernelGGL(coldot_reduce_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, part, T, P, out1,
                        out2);
-    return hip_check(hipGetLastError(), "row-dot reduce launch");
+    return hip_check(hipGetLastError(), "column-dot reduce launch");
 }
 
 } // namespace zp

@@ -11,8 +11,8 @@
 //   3. grad_c (+)= Z g                         (split-K GEMM, K = points, then a
 //                                               fixed-order reduction; chunks add
 //                                               in order)
-//   4. H = g c^T tile by tile (K = coefficient sets) with the epilogue
-//      grad_r[p] = sum_k H[p][k] dZ_k/dr(p), grad_theta likewise; H is never
+//   4. H^T = c g^T tile by tile (K = coefficient sets) with the epilogue
+//      grad_r[p] = sum_k H^T[k][p] dZ_k/dr(p), grad_theta likewise; H is never
 //      stored.  Per-tile partial sums are reduced in a fixed order.
 #include <algorithm>
 #include <cmath>
@@ -78,7 +78,7 @@ int splits_for(int64_t M, int64_t B, int64_t Kp, int ct)
 //            bf16, [Mp][Pcp] otherwise; backward without a cache: [Mp][Pcp])
 //   zr, zt : dZ/dr, dZ/dtheta of the chunk (backward without a cache)
 //   g, gt  : the chunk's upstream gradient [Pcp][Bp] (and [Bp][Pcp] for bf16)
-//   pc, pr : split-K partials of dL/dc and row-dot partials of dL/dr, dL/dtheta
+//   pc, pr : split-K partials of dL/dc and column-dot partials of dL/dr, dL/dtheta
 struct WsLayout {
     int64_t Mp, Bp, Pcp;
     int S, T;
@@ -90,7 +90,7 @@ struct WsLayout {
         Pcp = pad_up(Pc);
         const size_t e = ct_bytes(ct);
         S = splits_for(M, B, Pcp, ct);
-        T = (int)((M + rowdot_bn(ct) - 1) / rowdot_bn(ct));
+        T = (int)((M + coldot_bm(ct) - 1) / coldot_bm(ct));
         size_t o = 0;
         c_off = o;
         o += al(e * (size_t)Mp * (size_t)Bp);
@@ -395,15 +395,18 @@ zp_status zp_series_bwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
             if (st != ZP_OK) return st;
         }
         if (need_rt) {
+            // H^T = c g^T tile by tile (modes down, points across), reduced
+            // over the modes against dZ/dr and dZ/dtheta in the epilogue
             GemmDesc g{};
             g.ct = ct;
-            g.a = Operand{gbuf, Bp, pcp * Bp, LAY_KC}; // A(i=p, k=b) = g[p][b]
-            g.b = Operand{cbuf, Bp, Mp * Bp, LAY_KC};  // B(k=b, j=q) = c[q][b]
-            g.M = pc;
-            g.N = M;
+            g.a = Operand{cbuf, Bp, Mp * Bp, LAY_KC};  // A(i=q, k=b) = c[q][b]
+            g.b = Operand{gbuf, Bp, pcp * Bp, LAY_KC}; // B(k=b, j=p) = g[p][b]
+            g.M = M;
+            g.N = pc;
             g.K = Bp;
             g.splits = 1;
-            g.epi = EPI_ROWDOT;
+            g.epi = EPI_COLDOT;
+            g.order = 1; // tiles sharing a point panel of g run together
             g.D1 = zr;
             g.D2 = zt;
             g.ldd = ldz;
@@ -411,7 +414,7 @@ zp_status zp_series_bwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
             g.part = (double *)(ws + L.pr_off);
             st = launch_gemm(g, s);
             if (st != ZP_OK) return st;
-            st = launch_rowdot_reduce(g.part, (int)((M + rowdot_bn(ct) - 1) / rowdot_bn(ct)), pc,
+            st = launch_coldot_reduce(g.part, (int)((M + coldot_bm(ct) - 1) / coldot_bm(ct)), pc,
                                       d_grad_r ? d_grad_r + p0 : nullptr, d_grad_theta ? d_grad_theta + p0 : nullptr,
                                       s);
             if (st != ZP_OK) return st;
@@ -536,7 +539,7 @@ extern "C" zp_status zp_series_jvp(const int32_t *h_n, const int32_t *h_m, int64
 //   dL2/dc     = D g                                   (split-K, as grad_c)
 //   dL2/dr[p]  = sum_k dZ/dr_k(p) (g uc^T)[p][k] + sum_k Er_k(p) (g c^T)[p][k]
 //   dL2/dth[p] = sum_k dZ/dth_k(p) (g uc^T)[p][k] + sum_k Et_k(p) (g c^T)[p][k]
-// The last two are two row-dot contractions whose per-tile partials sit one
+// The last two are two column-dot contractions whose per-tile partials sit one
 // after the other and are reduced together in a fixed order.
 
 namespace {
@@ -552,7 +555,7 @@ struct Bwd2Layout {
         Pcp = pad_up(Pc);
         const size_t e = ct_bytes(ct), dsz = dsize_of(ct);
         S = splits_for(M, B, Pcp, ct);
-        T = (int)((M + rowdot_bn(ct) - 1) / rowdot_bn(ct));
+        T = (int)((M + coldot_bm(ct) - 1) / coldot_bm(ct));
         size_t o = 0;
         c_off = o;
         o += al(e * (size_t)Mp * (size_t)Bp);
@@ -634,8 +637,8 @@ zp_status zp_series_bwd2(const int32_t *h_n, const int32_t *h_m, int64_t M, cons
     const bool need_dir = d_ur != nullptr || d_ut != nullptr; // terms with ur, ut
     const bool want_rt = d_out_r || d_out_t;
     const bool run_c = d_out_c && need_dir;
-    const bool run_u = want_rt && need_u;   // row-dot against g uc^T with dZ/dr, dZ/dtheta
-    const bool run_e = want_rt && need_dir; // row-dot against g c^T with Er, Et
+    const bool run_u = want_rt && need_u;   // column-dot of uc g^T with dZ/dr, dZ/dtheta
+    const bool run_e = want_rt && need_dir; // column-dot of c g^T with Er, Et
     if (d_out_c && !need_dir) {
         st = launch_zero_pad(d_out_c, CT_F64, 0, 0, M, B, 0, s);
         if (st != ZP_OK) return st;
@@ -653,7 +656,7 @@ zp_status zp_series_bwd2(const int32_t *h_n, const int32_t *h_m, int64_t M, cons
     }
     const int zfmt = ct == CT_F64 ? F64 : ct == CT_F32 ? F32 : B16X3;
     const int dfmt = ct == CT_F64 ? F64 : F32;
-    const int BN = rowdot_bn(ct);
+    const int TM = coldot_bm(ct);
     for (int64_t p0 = 0; p0 < P; p0 += Pc) {
         const int64_t pc = std::min(Pc, P - p0);
         const int64_t pcp = pad_up(pc);
@@ -725,13 +728,14 @@ zp_status zp_series_bwd2(const int32_t *h_n, const int32_t *h_m, int64_t M, cons
                 if (which == 0 ? !run_u : !run_e) continue;
                 GemmDesc g{};
                 g.ct = ct;
-                g.a = Operand{gbuf, Bp, pcp * Bp, LAY_KC}; // A(i=p, k=b) = g[p][b]
-                g.b = Operand{ws + (which == 0 ? L.u_off : L.c_off), Bp, Mp * Bp, LAY_KC};
-                g.M = pc;
-                g.N = M;
+                g.a = Operand{ws + (which == 0 ? L.u_off : L.c_off), Bp, Mp * Bp, LAY_KC}; // A(i=q, k=b)
+                g.b = Operand{gbuf, Bp, pcp * Bp, LAY_KC};                               // B(k=b, j=p) = g[p][b]
+                g.M = M;
+                g.N = pc;
                 g.K = Bp;
                 g.splits = 1;
-                g.epi = EPI_ROWDOT;
+                g.epi = EPI_COLDOT;
+                g.order = 1;
                 g.D1 = ws + (which == 0 ? L.zr_off : L.er_off);
                 g.D2 = ws + (which == 0 ? L.zt_off : L.et_off);
                 g.ldd = pcp;
@@ -739,9 +743,9 @@ zp_status zp_series_bwd2(const int32_t *h_n, const int32_t *h_m, int64_t M, cons
                 g.part = part + (size_t)tiles * 2 * (size_t)pc;
                 st = launch_gemm(g, s);
                 if (st != ZP_OK) return st;
-                tiles += (int)((M + BN - 1) / BN);
+                tiles += (int)((M + TM - 1) / TM);
             }
-            st = launch_rowdot_reduce(part, tiles, pc, d_out_r ? d_out_r + p0 : nullptr,
+            st = launch_coldot_reduce(part, tiles, pc, d_out_r ? d_out_r + p0 : nullptr,
                                       d_out_t ? d_out_t + p0 : nullptr, s);
             if (st != ZP_OK) return st;
         }

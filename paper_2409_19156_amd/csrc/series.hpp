@@ -35,7 +35,7 @@ struct Operand {
 enum Epi : int {
     EPI_STORE = 0,   // C[i*ldc + j] = acc (FP64)
     EPI_PARTIAL = 1, // split-K: C + split*M*ldc, reduced later
-    EPI_ROWDOT = 2   // part[jtile][0|1][i] = sum_j acc(i,j) D1|D2[j*ldd + i]
+    EPI_COLDOT = 2   // part[itile][0|1][j] = sum_i acc(i,j) D1|D2[i*ldd + j]
 };
 
 struct GemmDesc {
@@ -46,15 +46,19 @@ struct GemmDesc {
     int epi;
     double *C;
     int64_t ldc;
-    const void *D1, *D2; // EPI_ROWDOT: derivative planes, FP64 or FP32
+    const void *D1, *D2; // EPI_COLDOT: derivative planes, FP64 or FP32
     int64_t ldd;
     bool d_f32;
-    double *part; // EPI_ROWDOT output partials [ceil(N/BN)][2][M]
+    double *part; // EPI_COLDOT output partials [ceil(M/BM)][2][N]
+    // Order of the output tiles over the launch: 0 = along a row of tiles
+    // first (workgroups in flight share an A panel), 1 = down a column of
+    // tiles first (they share a B panel).
+    int order;
 };
 
-// Column-tile width of the row-dot epilogue for a compute type (partials
-// buffer has ceil(N / rowdot_bn(ct)) tiles).
-int rowdot_bn(int ct);
+// Row-tile height of the column-dot epilogue for a compute type (its
+// partials buffer has ceil(M / coldot_bm(ct)) tiles).
+int coldot_bm(int ct);
 
 zp_status launch_gemm(const GemmDesc &g, hipStream_t s);
 
@@ -82,6 +86,6 @@ zp_status launch_splitk_reduce(const double *part, int S, int64_t M, int64_t N, 
                                bool accumulate, hipStream_t s);
 
 // out1[p] = sum_t part[t][0][p], out2[p] = sum_t part[t][1][p] (either nullable).
-zp_status launch_rowdot_reduce(const double *part, int T, int64_t P, double *out1, double *out2, hipStream_t s);
+zp_status launch_coldot_reduce(const double *part, int T, int64_t P, double *out1, double *out2, hipStream_t s);
 
 } // namespace zp
