@@ -328,7 +328,9 @@ template <int J, bool ANG, bool KB, int NPL, bool DIR = false, bool SEC = false>
 hipError_t launch(const Plan &plan, const double *r, const double *th, int64_t P, const Planes &o, hipStream_t s)
 {
     const int64_t tiles = (P + (int64_t)kBlock * NPL - 1) / ((int64_t)kBlock * NPL);
-    const bool use_pieces = tiles * (int64_t)plan.chains.size() < kMinWorkgroups;
+    // pieces when whole chains give too few workgroups, and while their count
+    // fits the grid's second dimension (chains: at most ZP_N_MAX + 1)
+    const bool use_pieces = tiles * (int64_t)plan.chains.size() < kMinWorkgroups && plan.pieces.size() <= 65535;
     const Chain *list = use_pieces ? plan.d_pieces : plan.d_chains;
     const size_t count = use_pieces ? plan.pieces.size() : plan.chains.size();
     const dim3 grid((unsigned)tiles, (unsigned)count);

@@ -188,3 +188,26 @@ def test_plan_cache_churn(zp):
             _lib.load().zp_cache_clear()
         for (n, m), ref in zip(reversed(lists), reversed(first)):
             assert torch.equal(zp.radial(n, m, r, 2), ref)
+
+
+def test_million_column_mode_list(zp, oracle_mod):
+    """1.1 million columns (every pair n <= 50 repeated 1630 times) on one
+    point tile: more chain pieces than a launch grid dimension holds, so the
+    launcher walks whole chains.  Every column equals its pair's oracle value."""
+    n1, m1 = W.radial_pairs(50)
+    reps = 1630
+    n = np.tile(n1, reps)
+    m = np.tile(m1, reps)
+    assert n.size > 16 * 65535
+    r = np.linspace(0.0, 1.0, 200)
+    ref = oracle_mod.radial(n1, m1, r, 0)[0]
+    out = zp.radial(n, m, _dev(r), 0)[0]
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    cols = np.concatenate([[0, n.size - 1], rng.choice(n.size, 4000, replace=False)])
+    got = out[torch.from_numpy(cols).cuda()].cpu().numpy()
+    assert np.all(np.abs(got - ref[cols % n1.size]) <= 1e-13)  # order 0: 1e-13 (n+1)^0
+    # repeated columns are bitwise equal
+    first = out[: n1.size].cpu().numpy()
+    last = out[-n1.size:].cpu().numpy()
+    assert np.array_equal(first, last)
