@@ -56,6 +56,7 @@ def _parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-series", action="store_true")
     ap.add_argument("--no-spectral3d", action="store_true")
+    ap.add_argument("--no-radial", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB, 5 times (for scaling "
                          "hardware byte counters), then exit")
@@ -132,6 +133,42 @@ def series_leg(steps: int, warmup: int):
     out["speedup_bf16x3_vs_fp64"] = out["fp64"]["ms_fwd_bwd"] / out["bf16x3"]["ms_fwd_bwd"]
     out["speedup_fp32_vs_fp64"] = out["fp64"]["ms_fwd_bwd"] / out["fp32"]["ms_fwd_bwd"]
     out["workload"] = "series_n64: ANSI n<=64 (2145 modes), 65536 disc points, 1024 sets, fwd+bwd (c, r, theta)"
+    return out
+
+
+def radial_legs(steps: int, warmup: int):
+    """The radial-only configurations: n <= 16 at 1002 points with orders 0..3
+    (launch-bound: entries/s only) and the n <= 200 stress set (10 201 pairs,
+    100 000 clustered points, orders 0..2: 3.06e9 entries, 24.5 GB written per
+    launch)."""
+    import torch
+
+    import paper_2409_19156_amd as zp
+    import zp_workloads as W
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+    for wl in (W.radial_n16(), W.radial_n200()):
+        r = torch.from_numpy(wl.r).to(dev)
+        buf = torch.empty((wl.max_dr + 1, wl.M, wl.P), dtype=torch.float64, device=dev)
+        for _ in range(warmup):
+            zp.radial(wl.n, wl.m, r, wl.max_dr, out=buf)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            zp.radial(wl.n, wl.m, r, wl.max_dr, out=buf)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        entries = buf.numel()
+        nbytes = entries * 8 + wl.P * 8
+        out[wl.name] = {"modes": wl.M, "points": wl.P, "orders": wl.max_dr + 1, "entries": entries,
+                        "ms_per_launch": ms, "entries_per_s": entries / (ms * 1e-3),
+                        "GBs": nbytes / (ms * 1e-3) / 1e9, "frac_of_hbm_peak": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del buf
+        torch.cuda.empty_cache()
     return out
 
 
@@ -293,6 +330,8 @@ def main():
         res["series"] = series_leg(steps=max(3, min(args.steps, 10)), warmup=2)
     if not args.no_spectral3d:
         res["spectral3d"] = spectral3d_leg(steps=max(3, min(args.steps, 10)), warmup=2)
+    if not args.no_radial:
+        res["radial"] = radial_legs(steps=max(3, min(args.steps, 10)), warmup=2)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_points)
     print(json.dumps(res), flush=True)
