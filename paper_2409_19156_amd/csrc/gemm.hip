@@ -58,6 +58,25 @@ template <> struct CTr<CT_BF3> {
     static constexpr int NP = 3;
 };
 
+__device__ __forceinline__ uint16_t bf16_rne(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ double bf16_val(uint16_t h) { return (double)__uint_as_float((uint32_t)h << 16); }
+
+// x = hi + mid + lo as three bf16 values (the residuals are exact in FP32).
+__device__ __forceinline__ void split3f(float x, uint32_t &h, uint32_t &m, uint32_t &l)
+{
+    h = bf16_rne(x);
+    const float r1 = x - __uint_as_float(h << 16);
+    m = bf16_rne(r1);
+    const float r2 = r1 - __uint_as_float(m << 16);
+    l = bf16_rne(r2);
+}
+
 // LDS geometry and global->LDS copy of one operand tile (X rows of the output
 // index by BK).  LDS holds the tile either as [X][BK] rows (k contiguous: the
 // k-contiguous and k-blocked layouts, and every bf16 operand) or as
@@ -89,12 +108,14 @@ template <int CT, int X, int BK, int LAY> struct Tile {
     static __device__ __forceinline__ int at(int x, int k) { return x * BK + (k ^ row_swizzle<CT>(x)); }
     static constexpr int VEC = 16 / (int)sizeof(T);
     // global tile as GROWS rows of GCOLS contiguous elements
-    static constexpr int GROWS = LAY == LAY_KC ? X : LAY == LAY_XC ? BK : BK / VEC;
-    static constexpr int GCOLS = LAY == LAY_KC ? BK : LAY == LAY_XC ? X : X * VEC;
+    static constexpr bool KC = LAY == LAY_KC || LAY == LAY_KC32;
+    static constexpr int GROWS = KC ? X : LAY == LAY_XC ? BK : BK / VEC;
+    static constexpr int GCOLS = KC ? BK : LAY == LAY_XC ? X : X * VEC;
     static constexpr int NV = GROWS * GCOLS / VEC;
     static constexpr int PER = NV / kThreads;
     static_assert(NV % kThreads == 0, "tile not divisible among threads");
     static_assert(LAY != LAY_KB8 || VEC == 8, "k-blocked layout is for bf16 operands");
+    static_assert(LAY != LAY_KC32 || CT == CT_BF3, "FP32-source layout is for bf16 operands");
 
     using Regs = u4[PER][CTr<CT>::NP];
 
@@ -114,6 +135,12 @@ template <int CT, int X, int BK, int LAY> struct Tile {
             int gr, gc;
             coords(v, gr, gc);
             int64_t off;
+            if (LAY == LAY_KC32) { // eight FP32 k values of one row, split at the LDS store
+                const float *fb = (const float *)base + (x0 + gr) * ld + (k0 + gc);
+                reg[v][0] = *(const u4 *)fb;
+                reg[v][1] = *(const u4 *)(fb + 4);
+                continue;
+            }
             if (LAY == LAY_KC)
                 off = (x0 + gr) * ld + (k0 + gc);
             else if (LAY == LAY_XC)
@@ -132,6 +159,24 @@ template <int CT, int X, int BK, int LAY> struct Tile {
         for (int v = 0; v < PER; ++v) {
             int gr, gc;
             coords(v, gr, gc);
+            if constexpr (LAY == LAY_KC32) {
+                // 8 floats -> hi, mid, lo planes of 8 bf16 each
+                u4 hp, mp, lp;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    uint32_t h0, m0, l0, h1, m1, l1;
+                    const uint32_t w0 = reg[v][q >> 1][(q & 1) * 2], w1 = reg[v][q >> 1][(q & 1) * 2 + 1];
+                    split3f(__uint_as_float(w0), h0, m0, l0);
+                    split3f(__uint_as_float(w1), h1, m1, l1);
+                    hp[q] = h0 | (h1 << 16);
+                    mp[q] = m0 | (m1 << 16);
+                    lp[q] = l0 | (l1 << 16);
+                }
+                *(u4 *)(lds + at(gr, gc)) = hp;
+                *(u4 *)(lds + ELEMS + at(gr, gc)) = mp;
+                *(u4 *)(lds + 2 * ELEMS + at(gr, gc)) = lp;
+                continue;
+            }
 #pragma unroll
             for (int p = 0; p < CTr<CT>::NP; ++p) {
                 T *L = lds + p * ELEMS;
@@ -439,7 +484,7 @@ hipError_t launch_e(const GemmDesc &g, hipStream_t s)
         }
     } else if constexpr (EPI == EPI_PARTIAL) {
         if constexpr (CT == CT_BF3) {
-            if (a == LAY_KC && b == LAY_KC) return launch_t<CT, LAY_KC, LAY_KC, EPI>(g, s);
+            if (a == LAY_KC32 && b == LAY_KC) return launch_t<CT, LAY_KC32, LAY_KC, EPI>(g, s);
         } else {
             if (a == LAY_KC && b == LAY_XC) return launch_t<CT, LAY_KC, LAY_XC, EPI>(g, s);
         }
@@ -460,15 +505,6 @@ hipError_t launch_c(const GemmDesc &g, hipStream_t s)
 }
 
 // ------------------------------------------------------------ helpers --
-
-__device__ __forceinline__ uint16_t bf16_rne(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
-__device__ __forceinline__ double bf16_val(uint16_t h) { return (double)__uint_as_float((uint32_t)h << 16); }
 
 __device__ __forceinline__ void put(void *dst, int ct, int64_t idx, int64_t sub, double v)
 {

@@ -30,9 +30,15 @@ namespace {
 
 int ct_of(int32_t prec) { return prec == ZP_FP64 ? CT_F64 : prec == ZP_FP32 ? CT_F32 : CT_BF3; }
 size_t dsize_of(int ct) { return ct == CT_F64 ? 8 : 4; } // dZ/dr, dZ/dtheta planes
+// Z as the backward's split-K contraction reads it: FP64, or FP32 (the bf16
+// contraction splits FP32 values into its three planes while loading them)
+int zct_of(int ct) { return ct == CT_F64 ? CT_F64 : CT_F32; }
+size_t zsize_of(int ct) { return ct == CT_F64 ? 8 : 4; }
+int zlay_of(int ct) { return ct == CT_BF3 ? LAY_KC32 : LAY_KC; }
 size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
-// Cache: Z in the contraction type [Mp][Pp], then dZ/dr and dZ/dtheta [M][Pp].
+// Cache: Z [Mp][Pp] (FP64; FP32 for the FP32 and bf16 contractions), then
+// dZ/dr and dZ/dtheta [M][Pp].
 struct CacheLayout {
     int64_t Mp, Pp;
     size_t z_off, zr_off, zt_off, total;
@@ -41,7 +47,7 @@ struct CacheLayout {
         Mp = pad_up(M);
         Pp = pad_up(P);
         z_off = 0;
-        zr_off = al(ct_bytes(ct) * (size_t)Mp * (size_t)Pp);
+        zr_off = al(zsize_of(ct) * (size_t)Mp * (size_t)Pp);
         zt_off = zr_off + al(dsize_of(ct) * (size_t)M * (size_t)Pp);
         total = zt_off + al(dsize_of(ct) * (size_t)M * (size_t)Pp);
     }
@@ -169,8 +175,8 @@ zp_status common_checks(const int32_t *n, const int32_t *m, int64_t M, int64_t P
     return ZP_OK;
 }
 
-// Basis of points [p0, p0+Pc) into [Mp][ld] planes: Z in the contraction type
-// (pad zeroed), dZ/dr and dZ/dtheta (if not null) in FP64 / FP32.
+// Basis of points [p0, p0+Pc) into [Mp][ld] planes: Z as the backward reads
+// it (zct_of; pad zeroed), dZ/dr and dZ/dtheta (if not null) in FP64 / FP32.
 zp_status basis_into(const Plan &plan, const double *r, const double *th, int64_t p0, int64_t Pc, int ct,
                      void *z, void *zr, void *zt, int64_t ld, int64_t Mp, int64_t M, hipStream_t s)
 {
@@ -178,13 +184,13 @@ zp_status basis_into(const Plan &plan, const double *r, const double *th, int64_
     o.ld = ld;
     o.sub = Mp * ld;
     o.plane[0] = z;
-    o.fmt[0] = ct == CT_F64 ? F64 : ct == CT_F32 ? F32 : B16X3;
+    o.fmt[0] = ct == CT_F64 ? F64 : F32;
     const int dfmt = ct == CT_F64 ? F64 : F32;
     o.plane[1] = zr;
     o.fmt[1] = dfmt;
     o.plane[4] = zt;
     o.fmt[4] = dfmt;
-    zp_status st = launch_zero_pad(z, ct, M, Pc, Mp, ld, Mp * ld, s);
+    zp_status st = launch_zero_pad(z, zct_of(ct), M, Pc, Mp, ld, Mp * ld, s);
     if (st != ZP_OK) return st;
     return launch_chain_kernel(plan, r + p0, th + p0, Pc, zr ? 1 : 0, true, o, s);
 }
@@ -246,9 +252,9 @@ zp_status zp_series_fwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
 
     const CacheLayout CL(M, P, ct);
     char *cache = (char *)d_cache;
-    const size_t esz = ct == CT_BF3 ? 2 : ct_bytes(ct);
+    const size_t zsz = zsize_of(ct); // the cache's Z element
     if (have_cache) {
-        st = launch_zero_pad(cache + CL.z_off, ct, M, P, Mp, CL.Pp, Mp * CL.Pp, s);
+        st = launch_zero_pad(cache + CL.z_off, zct_of(ct), M, P, Mp, CL.Pp, Mp * CL.Pp, s);
         if (st != ZP_OK) return st;
     }
     for (int64_t p0 = 0; p0 < P; p0 += Pc) {
@@ -261,8 +267,8 @@ zp_status zp_series_fwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
         if (have_cache) { // keep Z, dZ/dr, dZ/dtheta for the backward
             o.ld = CL.Pp;
             o.sub = Mp * CL.Pp;
-            o.plane[0] = cache + CL.z_off + esz * (size_t)p0;
-            o.fmt[0] = zfmt;
+            o.plane[0] = cache + CL.z_off + zsz * (size_t)p0;
+            o.fmt[0] = ct == CT_F64 ? F64 : F32;
             o.plane[1] = cache + CL.zr_off + dsize_of(ct) * (size_t)p0;
             o.fmt[1] = dfmt;
             o.plane[4] = cache + CL.zt_off + dsize_of(ct) * (size_t)p0;
@@ -292,7 +298,7 @@ zp_status zp_series_fwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
             g.a = Operand{ws + L.z_off, pcp, Mp * pcp, LAY_KB8}; // A(i = p, k = e)
             g.b = Operand{cbuf, Mp, Bp * Mp, LAY_KC};            // B(k = e, j = b)
         } else if (have_cache) {
-            g.a = Operand{cache + CL.z_off + esz * (size_t)p0, CL.Pp, Mp * CL.Pp, LAY_XC}; // A(i = p, k = q) = Z[q][p]
+            g.a = Operand{cache + CL.z_off + zsz * (size_t)p0, CL.Pp, Mp * CL.Pp, LAY_XC}; // A(i = p, k = q) = Z[q][p]
             g.b = Operand{cbuf, Bp, Mp * Bp, LAY_XC};
         } else {
             g.a = Operand{ws + L.z_off, pcp, Mp * pcp, LAY_XC};
@@ -344,7 +350,7 @@ zp_status zp_series_bwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
         if (st != ZP_OK) return st;
     }
     const CacheLayout CL(M, P, ct);
-    const size_t esz = ct == CT_BF3 ? 2 : ct_bytes(ct);
+    const size_t zsz = zsize_of(ct);
     for (int64_t p0 = 0; p0 < P; p0 += Pc) {
         const int64_t pc = std::min(Pc, P - p0);
         const int64_t pcp = pad_up(pc);
@@ -352,7 +358,7 @@ zp_status zp_series_bwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
         int64_t ldz, zsub;
         if (have_cache) {
             const char *cache = (const char *)d_cache;
-            z = cache + CL.z_off + esz * (size_t)p0;
+            z = cache + CL.z_off + zsz * (size_t)p0;
             zr = cache + CL.zr_off + dsize_of(ct) * (size_t)p0;
             zt = cache + CL.zt_off + dsize_of(ct) * (size_t)p0;
             ldz = CL.Pp;
@@ -377,7 +383,7 @@ zp_status zp_series_bwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
         if (d_grad_c) {
             GemmDesc g{};
             g.ct = ct;
-            g.a = Operand{z, ldz, zsub, LAY_KC}; // A(i=q, k=p) = Z[q][p]
+            g.a = Operand{z, ldz, zsub, zlay_of(ct)}; // A(i=q, k=p) = Z[q][p]
             if (ct == CT_BF3)
                 g.b = Operand{ws + L.gt_off, pcp, Bp * pcp, LAY_KC}; // B(k=p, j=b) = g^T[b][p]
             else
@@ -654,7 +660,7 @@ zp_status zp_series_bwd2(const int32_t *h_n, const int32_t *h_m, int64_t M, cons
         st = launch_convert(d_uc, M, B, B, ct, ws + L.u_off, Bp, Mp, Mp * Bp, false, s);
         if (st != ZP_OK) return st;
     }
-    const int zfmt = ct == CT_F64 ? F64 : ct == CT_F32 ? F32 : B16X3;
+    const int zfmt = ct == CT_F64 ? F64 : F32; // D as the split-K contraction reads it
     const int dfmt = ct == CT_F64 ? F64 : F32;
     const int TM = coldot_bm(ct);
     for (int64_t p0 = 0; p0 < P; p0 += Pc) {
@@ -677,7 +683,7 @@ zp_status zp_series_bwd2(const int32_t *h_n, const int32_t *h_m, int64_t M, cons
             o.fmt[4] = dfmt;
         }
         if (run_c) {
-            st = launch_zero_pad(ws + L.d_off, ct, M, pc, Mp, pcp, Mp * pcp, s);
+            st = launch_zero_pad(ws + L.d_off, zct_of(ct), M, pc, Mp, pcp, Mp * pcp, s);
             if (st != ZP_OK) return st;
             o.dir = ws + L.d_off;
             o.dir_fmt = zfmt;
@@ -704,7 +710,7 @@ zp_status zp_series_bwd2(const int32_t *h_n, const int32_t *h_m, int64_t M, cons
             }
             GemmDesc g{};
             g.ct = ct;
-            g.a = Operand{ws + L.d_off, pcp, Mp * pcp, LAY_KC}; // A(i=q, k=p) = D[q][p]
+            g.a = Operand{ws + L.d_off, pcp, Mp * pcp, zlay_of(ct)}; // A(i=q, k=p) = D[q][p]
             if (ct == CT_BF3)
                 g.b = Operand{ws + L.gt_off, pcp, Bp * pcp, LAY_KC};
             else

@@ -22,7 +22,9 @@ inline int64_t pad_up(int64_t x) { return (x + kPad - 1) / kPad * kPad; }
 //   LAY_KC  : base[x*ld + k]                      (contiguous along k)
 //   LAY_XC  : base[k*ld + x]                      (contiguous along x)
 //   LAY_KB8 : base[((k/8)*ld + x)*8 + k%8]        (k in blocks of eight)
-enum Layout : int { LAY_KC = 0, LAY_XC = 1, LAY_KB8 = 2 };
+//   LAY_KC32: as LAY_KC, but FP32 values of a BF3 operand; the GEMM splits
+//             them into the three bf16 planes on the way into LDS
+enum Layout : int { LAY_KC = 0, LAY_XC = 1, LAY_KB8 = 2, LAY_KC32 = 3 };
 
 // Operand of C(i,j) = sum_k A(i,k) B(k,j); `sub` separates the BF3 planes.
 struct Operand {

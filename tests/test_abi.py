@@ -124,8 +124,8 @@ def test_size_queries(lib):
         assert 0 < mn.value <= full.value
         assert full.value % 256 == 0 and mn.value % 256 == 0
         assert lib.zp_series_cache_bytes(2145, 65536, prec, ctypes.byref(cb)) == OK
-        # at least Z in the contraction type plus two derivative planes
-        per = {0: 8 + 16, 1: 4 + 8, 2: 6 + 8}[prec]
+        # at least Z (FP64, or FP32 for the FP32 and bf16 contractions) plus two derivative planes
+        per = {0: 8 + 16, 1: 4 + 8, 2: 4 + 8}[prec]
         assert cb.value >= 2145 * 65536 * per
     assert lib.zp_series_workspace(-1, 4, 4, 0, ctypes.byref(full), None) == ERR_ARG
     assert lib.zp_series_workspace(4, 4, 4, 9, ctypes.byref(full), None) == ERR_PREC
