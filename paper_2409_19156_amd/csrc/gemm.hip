@@ -218,7 +218,7 @@ template <> struct Cfg<CT_BF3> {
 };
 
 template <int CT, int ALAY, int BLAY, int EPI>
-__global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc g)
+__device__ __forceinline__ void gemm_body(const GemmDesc &g)
 {
     using C = Cfg<CT>;
     constexpr int BM = C::BM, BN = C::BN, BK = C::BK, WM = C::WM, WN = C::WN;
@@ -461,12 +461,31 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc g)
 }
 
 template <int CT, int ALAY, int BLAY, int EPI>
+__global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc g)
+{
+    gemm_body<CT, ALAY, BLAY, EPI>(g);
+}
+
+// The same kernel compiled for four waves per SIMD (at most 128 registers), so
+// that two 512-thread workgroups share a CU.  Used where the body fits without
+// spilling: the FP64 forward (measured 6% faster; the other FP64 and FP32
+// instances would spill and lose more than they gain).
+template <int CT, int ALAY, int BLAY, int EPI>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void gemm_kernel_w4(GemmDesc g)
+{
+    gemm_body<CT, ALAY, BLAY, EPI>(g);
+}
+
+template <int CT, int ALAY, int BLAY, int EPI>
 hipError_t launch_t(const GemmDesc &g, hipStream_t s)
 {
     using C = Cfg<CT>;
     const dim3 grid((unsigned)((g.M + C::BM - 1) / C::BM), (unsigned)((g.N + C::BN - 1) / C::BN),
                     (unsigned)g.splits);
-    hipLaunchKernelGGL((gemm_kernel<CT, ALAY, BLAY, EPI>), grid, dim3(kThreads), 0, s, g);
+    if constexpr (CT == CT_F64 && EPI == EPI_STORE)
+        hipLaunchKernelGGL((gemm_kernel_w4<CT, ALAY, BLAY, EPI>), grid, dim3(kThreads), 0, s, g);
+    else
+        hipLaunchKernelGGL((gemm_kernel<CT, ALAY, BLAY, EPI>), grid, dim3(kThreads), 0, s, g);
     return hipGetLastError();
 }
 
