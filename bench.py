@@ -57,6 +57,7 @@ def _parse():
     ap.add_argument("--no-series", action="store_true")
     ap.add_argument("--no-spectral3d", action="store_true")
     ap.add_argument("--no-radial", action="store_true")
+    ap.add_argument("--no-ad", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB, 5 times (for scaling "
                          "hardware byte counters), then exit")
@@ -168,6 +169,56 @@ def radial_legs(steps: int, warmup: int):
                         "ms_per_launch": ms, "entries_per_s": entries / (ms * 1e-3),
                         "GBs": nbytes / (ms * 1e-3) / 1e9, "frac_of_hbm_peak": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         del buf
+        torch.cuda.empty_cache()
+    return out
+
+
+def ad_analysis_leg(steps: int, warmup: int):
+    """Forward-mode and second-order derivatives of the series on the n <= 64
+    workload (2145 modes, 65 536 points, 1024 sets), and the analysis transform
+    on a 256 x 512 quadrature grid (131 072 points, 1024 sets), per precision.
+    Algorithmic contraction work: JVP 2 x 2PMB (the stacked K = 2M), second-order
+    adjoint 4 x 2PMB (split-K, two column-dots, and the JVP's 2), analysis 2PMB."""
+    import torch
+
+    import paper_2409_19156_amd as zp
+    import zp_workloads as W
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    wl = W.series_n64()
+    r, th = torch.from_numpy(wl.r).to(dev), torch.from_numpy(wl.theta).to(dev)
+    c, g = torch.from_numpy(wl.c).to(dev), torch.from_numpy(wl.g).to(dev)
+    rng = np.random.default_rng(7)
+    tc = torch.from_numpy(rng.standard_normal(wl.c.shape) / (wl.n + 1.0)[:, None]).to(dev)
+    tr = torch.from_numpy(rng.standard_normal(wl.P)).to(dev)
+    tt = torch.from_numpy(rng.standard_normal(wl.P)).to(dev)
+    ra, tha, wa = zp.analysis_grid(256, 512)
+    ra, tha, wa = (torch.from_numpy(x).to(dev) for x in (ra, tha, wa))
+    fa = torch.from_numpy(rng.standard_normal((ra.numel(), wl.B))).to(dev)
+    unit = 2.0 * wl.P * wl.M * wl.B / 1e9
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    out = {"workload": "series_n64 (JVP, second-order adjoint); analysis on 256 x 512 Gauss-Legendre x trapezoid "
+                       "points, 1024 sets"}
+    for prec in ("fp64", "bf16x3"):
+        ms_jvp = timed(lambda: zp.series_jvp(wl.n, wl.m, r, th, c, tc, tr, tt, prec))
+        ms_b2 = timed(lambda: zp.series_backward2(wl.n, wl.m, r, th, c, g, tc, tr, tt, prec))
+        ms_an = timed(lambda: zp.series_analysis(wl.n, wl.m, ra, tha, wa, fa, prec))
+        an_gf = 2.0 * ra.numel() * wl.M * wl.B / 1e9
+        out[prec] = {"ms_jvp": ms_jvp, "jvp_tflops": 2 * unit / ms_jvp, "ms_bwd2": ms_b2,
+                     "bwd2_tflops": 4 * unit / ms_b2, "ms_analysis": ms_an, "analysis_tflops": an_gf / ms_an}
         torch.cuda.empty_cache()
     return out
 
@@ -332,6 +383,8 @@ def main():
         res["spectral3d"] = spectral3d_leg(steps=max(3, min(args.steps, 10)), warmup=2)
     if not args.no_radial:
         res["radial"] = radial_legs(steps=max(3, min(args.steps, 10)), warmup=2)
+    if not args.no_ad:
+        res["ad_analysis"] = ad_analysis_leg(steps=max(3, min(args.steps, 5)), warmup=1)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_points)
     print(json.dumps(res), flush=True)
