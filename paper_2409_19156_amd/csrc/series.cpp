@@ -17,6 +17,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <vector>
 
 #include "series.hpp"
 
@@ -175,6 +177,52 @@ zp_status common_checks(const int32_t *n, const int32_t *m, int64_t M, int64_t P
     return ZP_OK;
 }
 
+// A second stream per device for the forward's pipeline (created once, at the
+// default priority, never destroyed: no HIP call at static destruction).
+hipStream_t helper_stream()
+{
+    static std::mutex mu;
+    static hipStream_t streams[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+        streams[dev] = nullptr;
+    return streams[dev];
+}
+
+// Compute units of the current device (cached per device; 0 if unknown).
+int device_cus()
+{
+    static std::mutex mu;
+    static int cus[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!cus[dev] && hipDeviceGetAttribute(&cus[dev], hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus[dev] = 0;
+    return cus[dev];
+}
+
+// Forward pipeline: chunks of points alternate between the caller's stream
+// and the helper stream; chunk i+1's basis starts when chunk i's basis has
+// finished, so it runs under chunk i's contraction.  A chunk's contraction
+// has one 128 x 128 output tile per compute unit (two for bf16, whose tiles
+// take a whole unit each), which leaves room beside it for the next basis:
+// with 65536 points x 1024 sets that is 16 chunks for FP64 and FP32 and 8
+// for bf16, the fastest of 1 to 32 chunks on the series of n <= 64.
+// Returns the chunk length, or 0 for no pipeline.
+int64_t pipe_chunk(int64_t P, int64_t B, int ct)
+{
+    constexpr int64_t kMinChunk = 2048, kMinPoints = 8192, kTile = 128;
+    const int cus = device_cus();
+    if (cus <= 0 || P < kMinPoints) return 0;
+    const int64_t col_tiles = (B + kTile - 1) / kTile;
+    const int64_t tiles = (ct == CT_BF3 ? 2 : 1) * (int64_t)cus;
+    const int64_t len = std::max(kMinChunk, (tiles + col_tiles - 1) / col_tiles * kTile);
+    return 2 * len <= P ? len : 0;
+}
+
 // Basis of points [p0, p0+Pc) into [Mp][ld] planes: Z as the backward reads
 // it (zct_of; pad zeroed), dZ/dr and dZ/dtheta (if not null) in FP64 / FP32.
 zp_status basis_into(const Plan &plan, const double *r, const double *th, int64_t p0, int64_t Pc, int ct,
@@ -233,12 +281,30 @@ zp_status zp_series_fwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
     if ((uintptr_t)d_cache & 255) return set_error(ZP_ERR_ARG, "cache must be 256-byte aligned");
     const int ct = ct_of(prec);
     const bool have_cache = d_cache != nullptr;
-    const int64_t Pc = chunk_for(M, P, B, ct, true, false, have_cache, ws_bytes);
+    int64_t Pc = chunk_for(M, P, B, ct, true, false, have_cache, ws_bytes);
     if (Pc <= 0) return set_error(ZP_ERR_WORKSPACE, "workspace smaller than the minimum (zp_series_workspace)");
     hipStream_t s = (hipStream_t)stream;
     std::shared_ptr<Plan> plan;
     st = get_plan(h_n, h_m, M, &plan);
     if (st != ZP_OK) return st;
+
+    // Pipelined chunks when the points are many and the workspace holds two
+    // chunk buffers for the basis (bf16, or no cache); otherwise one stream.
+    const bool ws_z = ct == CT_BF3 || !have_cache; // the basis goes through the workspace
+    bool pipe = false;
+    size_t zbuf = 0; // bytes of one chunk's basis buffer
+    const int64_t Pq = Pc == P ? pipe_chunk(P, B, ct) : 0;
+    if (Pq > 0) {
+        const WsLayout Lq(M, Pq, B, ct, true, false, have_cache);
+        zbuf = al(ct_bytes(ct) * (size_t)pad_up(M) * (size_t)Pq);
+        if (!ws_z || Lq.total + zbuf <= ws_bytes) {
+            pipe = true;
+            Pc = Pq;
+        }
+    }
+    hipStream_t h = pipe ? helper_stream() : nullptr;
+    if (!h) pipe = false;
+    if (!pipe) Pc = chunk_for(M, P, B, ct, true, false, have_cache, ws_bytes);
 
     const WsLayout L(M, Pc, B, ct, true, false, have_cache);
     char *ws = (char *)d_ws;
@@ -257,9 +323,44 @@ zp_status zp_series_fwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
         st = launch_zero_pad(cache + CL.z_off, zct_of(ct), M, P, Mp, CL.Pp, Mp * CL.Pp, s);
         if (st != ZP_OK) return st;
     }
-    for (int64_t p0 = 0; p0 < P; p0 += Pc) {
+    // pipeline events: fork (after the setup above), one per chunk's basis, join
+    std::vector<hipEvent_t> ev;
+    auto make_event = [&ev](hipEvent_t *e) {
+        zp_status r = hip_check(hipEventCreateWithFlags(e, hipEventDisableTiming), "hipEventCreate");
+        if (r == ZP_OK) ev.push_back(*e);
+        return r;
+    };
+    auto cleanup = [&ev]() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e); // released once completed
+    };
+    hipEvent_t prev_basis = nullptr;
+    if (pipe) {
+        hipEvent_t fork;
+        st = make_event(&fork);
+        if (st == ZP_OK) st = hip_check(hipEventRecord(fork, s), "hipEventRecord");
+        if (st == ZP_OK) st = hip_check(hipStreamWaitEvent(h, fork, 0), "hipStreamWaitEvent");
+        if (st != ZP_OK) {
+            cleanup();
+            return st;
+        }
+    }
+    int chunk = 0;
+    for (int64_t p0 = 0; p0 < P; p0 += Pc, ++chunk) {
         const int64_t pc = std::min(Pc, P - p0);
         const int64_t pcp = pad_up(pc);
+        hipStream_t cs = s;
+        char *zb = ws + L.z_off; // this chunk's basis buffer
+        if (pipe) {
+            cs = (chunk & 1) ? h : s;
+            zb += (chunk & 1) ? zbuf : 0; // chunk i+2 reuses chunk i's buffer on the same stream
+            if (prev_basis) {
+                st = hip_check(hipStreamWaitEvent(cs, prev_basis, 0), "hipStreamWaitEvent");
+                if (st != ZP_OK) {
+                    cleanup();
+                    return st;
+                }
+            }
+        }
         Planes o{};
         const int zfmt = ct == CT_F64 ? F64 : ct == CT_F32 ? F32 : B16X3;
         const int dfmt = ct == CT_F64 ? F64 : F32;
@@ -277,31 +378,40 @@ zp_status zp_series_fwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
         } else if (ct != CT_BF3) {
             o.ld = pcp;
             o.sub = Mp * pcp;
-            o.plane[0] = ws + L.z_off;
+            o.plane[0] = zb;
             o.fmt[0] = zfmt;
-            st = launch_zero_pad(ws + L.z_off, ct, M, pc, Mp, pcp, Mp * pcp, s);
+            st = launch_zero_pad(zb, ct, M, pc, Mp, pcp, Mp * pcp, cs);
             if (st != ZP_OK) return st;
         }
         if (ct == CT_BF3) {
-            o.kb = ws + L.z_off;
+            o.kb = zb;
             o.kb_ld = pcp;
             o.kb_sub = Mp * pcp;
-            st = launch_zero_kb8(o.kb, M, Mp, pc, pcp, Mp * pcp, s);
+            st = launch_zero_kb8(o.kb, M, Mp, pc, pcp, Mp * pcp, cs);
             if (st != ZP_OK) return st;
         }
-        st = launch_chain_kernel(*plan, d_r + p0, d_theta + p0, pc, J, true, o, s);
-        if (st != ZP_OK) return st;
+        st = launch_chain_kernel(*plan, d_r + p0, d_theta + p0, pc, J, true, o, cs);
+        if (st == ZP_OK && pipe) { // the next chunk's basis may start now
+            hipEvent_t done;
+            st = make_event(&done);
+            if (st == ZP_OK) st = hip_check(hipEventRecord(done, cs), "hipEventRecord");
+            prev_basis = done;
+        }
+        if (st != ZP_OK) {
+            cleanup();
+            return st;
+        }
 
         GemmDesc g{};
         g.ct = ct;
         if (ct == CT_BF3) {
-            g.a = Operand{ws + L.z_off, pcp, Mp * pcp, LAY_KB8}; // A(i = p, k = e)
+            g.a = Operand{zb, pcp, Mp * pcp, LAY_KB8}; // A(i = p, k = e)
             g.b = Operand{cbuf, Mp, Bp * Mp, LAY_KC};            // B(k = e, j = b)
         } else if (have_cache) {
             g.a = Operand{cache + CL.z_off + zsz * (size_t)p0, CL.Pp, Mp * CL.Pp, LAY_XC}; // A(i = p, k = q) = Z[q][p]
             g.b = Operand{cbuf, Bp, Mp * Bp, LAY_XC};
         } else {
-            g.a = Operand{ws + L.z_off, pcp, Mp * pcp, LAY_XC};
+            g.a = Operand{zb, pcp, Mp * pcp, LAY_XC};
             g.b = Operand{cbuf, Bp, Mp * Bp, LAY_XC};
         }
         g.M = pc;
@@ -311,9 +421,20 @@ zp_status zp_series_fwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
         g.epi = EPI_STORE;
         g.C = d_f + p0 * B;
         g.ldc = B;
-        st = launch_gemm(g, s);
-        if (st != ZP_OK) return st;
+        st = launch_gemm(g, cs);
+        if (st != ZP_OK) {
+            cleanup();
+            return st;
+        }
     }
+    if (pipe) { // join: the caller's stream waits for the helper's last chunk
+        hipEvent_t join;
+        st = make_event(&join);
+        if (st == ZP_OK) st = hip_check(hipEventRecord(join, h), "hipEventRecord");
+        if (st == ZP_OK) st = hip_check(hipStreamWaitEvent(s, join, 0), "hipStreamWaitEvent");
+    }
+    cleanup();
+    if (st != ZP_OK) return st;
     return ZP_OK;
 }
 
