@@ -223,6 +223,60 @@ int64_t pipe_chunk(int64_t P, int64_t B, int ct)
     return 2 * len <= P ? len : 0;
 }
 
+// Chunks of a basis-then-contraction loop on two streams: chunk i runs on
+// the caller's stream (even i) or the helper stream (odd i), and its basis
+// waits for chunk i-1's basis, so that it runs under chunk i-1's contraction.
+// Chunk i+2 may reuse chunk i's workspace buffer: they share a stream.  The
+// helper stream forks from the caller's stream at start() and joins it at
+// finish().  Switched off, every chunk runs on the caller's stream.
+class ChunkPipe {
+public:
+    ChunkPipe(hipStream_t s, bool on) : s_(s), h_(on ? helper_stream() : nullptr) {}
+    ~ChunkPipe()
+    {
+        for (hipEvent_t e : ev_) (void)hipEventDestroy(e); // released once completed
+    }
+    ChunkPipe(const ChunkPipe &) = delete;
+    ChunkPipe &operator=(const ChunkPipe &) = delete;
+
+    bool on() const { return h_ != nullptr; }
+    hipStream_t stream(int chunk) const { return on() && (chunk & 1) ? h_ : s_; }
+    zp_status start()
+    {
+        hipEvent_t e = nullptr;
+        zp_status st = on() ? record(s_, &e) : ZP_OK;
+        return e ? wait(h_, e) : st;
+    }
+    zp_status before_basis(int chunk) { return on() && prev_ ? wait(stream(chunk), prev_) : ZP_OK; }
+    zp_status after_basis(int chunk) { return on() ? record(stream(chunk), &prev_) : ZP_OK; }
+    zp_status finish()
+    {
+        hipEvent_t e = nullptr;
+        zp_status st = on() ? record(h_, &e) : ZP_OK;
+        return e ? wait(s_, e) : st;
+    }
+
+private:
+    zp_status record(hipStream_t st, hipEvent_t *out)
+    {
+        hipEvent_t e;
+        zp_status r = hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+        if (r != ZP_OK) return r;
+        ev_.push_back(e);
+        r = hip_check(hipEventRecord(e, st), "hipEventRecord");
+        if (r == ZP_OK) *out = e;
+        return r;
+    }
+    static zp_status wait(hipStream_t st, hipEvent_t e)
+    {
+        return hip_check(hipStreamWaitEvent(st, e, 0), "hipStreamWaitEvent");
+    }
+
+    hipStream_t s_, h_;
+    hipEvent_t prev_ = nullptr;
+    std::vector<hipEvent_t> ev_;
+};
+
 // Basis of points [p0, p0+Pc) into [Mp][ld] planes: Z as the backward reads
 // it (zct_of; pad zeroed), dZ/dr and dZ/dtheta (if not null) in FP64 / FP32.
 zp_status basis_into(const Plan &plan, const double *r, const double *th, int64_t p0, int64_t Pc, int ct,
@@ -302,9 +356,8 @@ zp_status zp_series_fwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
             Pc = Pq;
         }
     }
-    hipStream_t h = pipe ? helper_stream() : nullptr;
-    if (!h) pipe = false;
-    if (!pipe) Pc = chunk_for(M, P, B, ct, true, false, have_cache, ws_bytes);
+    ChunkPipe pipeline(s, pipe);
+    if (!pipeline.on()) Pc = chunk_for(M, P, B, ct, true, false, have_cache, ws_bytes);
 
     const WsLayout L(M, Pc, B, ct, true, false, have_cache);
     char *ws = (char *)d_ws;
@@ -323,44 +376,16 @@ zp_status zp_series_fwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
         st = launch_zero_pad(cache + CL.z_off, zct_of(ct), M, P, Mp, CL.Pp, Mp * CL.Pp, s);
         if (st != ZP_OK) return st;
     }
-    // pipeline events: fork (after the setup above), one per chunk's basis, join
-    std::vector<hipEvent_t> ev;
-    auto make_event = [&ev](hipEvent_t *e) {
-        zp_status r = hip_check(hipEventCreateWithFlags(e, hipEventDisableTiming), "hipEventCreate");
-        if (r == ZP_OK) ev.push_back(*e);
-        return r;
-    };
-    auto cleanup = [&ev]() {
-        for (hipEvent_t e : ev) (void)hipEventDestroy(e); // released once completed
-    };
-    hipEvent_t prev_basis = nullptr;
-    if (pipe) {
-        hipEvent_t fork;
-        st = make_event(&fork);
-        if (st == ZP_OK) st = hip_check(hipEventRecord(fork, s), "hipEventRecord");
-        if (st == ZP_OK) st = hip_check(hipStreamWaitEvent(h, fork, 0), "hipStreamWaitEvent");
-        if (st != ZP_OK) {
-            cleanup();
-            return st;
-        }
-    }
+    st = pipeline.start();
+    if (st != ZP_OK) return st;
     int chunk = 0;
     for (int64_t p0 = 0; p0 < P; p0 += Pc, ++chunk) {
         const int64_t pc = std::min(Pc, P - p0);
         const int64_t pcp = pad_up(pc);
-        hipStream_t cs = s;
-        char *zb = ws + L.z_off; // this chunk's basis buffer
-        if (pipe) {
-            cs = (chunk & 1) ? h : s;
-            zb += (chunk & 1) ? zbuf : 0; // chunk i+2 reuses chunk i's buffer on the same stream
-            if (prev_basis) {
-                st = hip_check(hipStreamWaitEvent(cs, prev_basis, 0), "hipStreamWaitEvent");
-                if (st != ZP_OK) {
-                    cleanup();
-                    return st;
-                }
-            }
-        }
+        hipStream_t cs = pipeline.stream(chunk);
+        char *zb = ws + L.z_off + (pipeline.on() && (chunk & 1) ? zbuf : 0); // this chunk's basis buffer
+        st = pipeline.before_basis(chunk);
+        if (st != ZP_OK) return st;
         Planes o{};
         const int zfmt = ct == CT_F64 ? F64 : ct == CT_F32 ? F32 : B16X3;
         const int dfmt = ct == CT_F64 ? F64 : F32;
@@ -391,16 +416,9 @@ zp_status zp_series_fwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
             if (st != ZP_OK) return st;
         }
         st = launch_chain_kernel(*plan, d_r + p0, d_theta + p0, pc, J, true, o, cs);
-        if (st == ZP_OK && pipe) { // the next chunk's basis may start now
-            hipEvent_t done;
-            st = make_event(&done);
-            if (st == ZP_OK) st = hip_check(hipEventRecord(done, cs), "hipEventRecord");
-            prev_basis = done;
-        }
-        if (st != ZP_OK) {
-            cleanup();
-            return st;
-        }
+        if (st != ZP_OK) return st;
+        st = pipeline.after_basis(chunk); // the next chunk's basis may start now
+        if (st != ZP_OK) return st;
 
         GemmDesc g{};
         g.ct = ct;
@@ -422,20 +440,9 @@ zp_status zp_series_fwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
         g.C = d_f + p0 * B;
         g.ldc = B;
         st = launch_gemm(g, cs);
-        if (st != ZP_OK) {
-            cleanup();
-            return st;
-        }
+        if (st != ZP_OK) return st;
     }
-    if (pipe) { // join: the caller's stream waits for the helper's last chunk
-        hipEvent_t join;
-        st = make_event(&join);
-        if (st == ZP_OK) st = hip_check(hipEventRecord(join, h), "hipEventRecord");
-        if (st == ZP_OK) st = hip_check(hipStreamWaitEvent(s, join, 0), "hipStreamWaitEvent");
-    }
-    cleanup();
-    if (st != ZP_OK) return st;
-    return ZP_OK;
+    return pipeline.finish();
 }
 
 zp_status zp_series_bwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r, const double *d_theta,
@@ -569,11 +576,16 @@ extern "C" zp_status zp_series_jvp(const int32_t *h_n, const int32_t *h_m, int64
         return launch_zero_pad(d_tf, CT_F64, 0, 0, P, B, 0, s);
     if (!d_ws || ((uintptr_t)d_ws & 255)) return set_error(ZP_ERR_ARG, "workspace must be non-null and 256-byte aligned");
     const int ct = ct_of(prec);
-    const int64_t Pc = jvp_chunk_for(M, P, B, ct, ws_bytes);
+    int64_t Pc = jvp_chunk_for(M, P, B, ct, ws_bytes);
     if (Pc <= 0) return set_error(ZP_ERR_WORKSPACE, "workspace smaller than the minimum (zp_series_workspace)");
     std::shared_ptr<Plan> plan;
     st = get_plan(h_n, h_m, M, &plan);
     if (st != ZP_OK) return st;
+    // pipelined chunks when the workspace holds two chunk buffers (as the forward)
+    const int64_t Pq = Pc == P ? pipe_chunk(P, B, ct) : 0;
+    const size_t zstride = Pq > 0 ? al(ct_bytes(ct) * (size_t)(2 * pad_up(M)) * (size_t)Pq) : 0;
+    ChunkPipe pipeline(s, Pq > 0 && JvpLayout(M, Pq, B, ct).total + zstride <= ws_bytes);
+    if (pipeline.on()) Pc = Pq;
 
     const int64_t Mp = pad_up(M), Bp = pad_up(B);
     const int nblk = (with_c ? 1 : 0) + (with_dir ? 1 : 0);
@@ -595,10 +607,16 @@ extern "C" zp_status zp_series_jvp(const int32_t *h_n, const int32_t *h_m, int64
         if (st != ZP_OK) return st;
         ++blk;
     }
-    for (int64_t p0 = 0; p0 < P; p0 += Pc) {
+    st = pipeline.start();
+    if (st != ZP_OK) return st;
+    int chunk = 0;
+    for (int64_t p0 = 0; p0 < P; p0 += Pc, ++chunk) {
         const int64_t pc = std::min(Pc, P - p0);
         const int64_t pcp = pad_up(pc);
-        char *zbuf = ws + L.z_off;
+        const hipStream_t cs = pipeline.stream(chunk);
+        char *zbuf = ws + L.z_off + (pipeline.on() && (chunk & 1) ? zstride : 0);
+        st = pipeline.before_basis(chunk);
+        if (st != ZP_OK) return st;
         Planes o{};
         o.ld = pcp;
         const int zfmt = ct == CT_F64 ? F64 : F32;
@@ -606,7 +624,7 @@ extern "C" zp_status zp_series_jvp(const int32_t *h_n, const int32_t *h_m, int64
             o.kb_ld = pcp;
             o.kb_sub = K * pcp;
             for (int b2 = 0; b2 < nblk; ++b2) {
-                st = launch_zero_kb8(zbuf + esz * (size_t)(b2 * Mp) * (size_t)pcp, M, Mp, pc, pcp, K * pcp, s);
+                st = launch_zero_kb8(zbuf + esz * (size_t)(b2 * Mp) * (size_t)pcp, M, Mp, pc, pcp, K * pcp, cs);
                 if (st != ZP_OK) return st;
             }
             if (with_c) o.kb = zbuf;
@@ -614,7 +632,7 @@ extern "C" zp_status zp_series_jvp(const int32_t *h_n, const int32_t *h_m, int64
         } else {
             o.sub = K * pcp;
             for (int b2 = 0; b2 < nblk; ++b2) {
-                st = launch_zero_pad(zbuf + esz * (size_t)(b2 * Mp) * (size_t)pcp, ct, M, pc, Mp, pcp, 0, s);
+                st = launch_zero_pad(zbuf + esz * (size_t)(b2 * Mp) * (size_t)pcp, ct, M, pc, Mp, pcp, 0, cs);
                 if (st != ZP_OK) return st;
             }
             if (with_c) {
@@ -630,7 +648,9 @@ extern "C" zp_status zp_series_jvp(const int32_t *h_n, const int32_t *h_m, int64
             o.dir_r = d_tr ? d_tr + p0 : nullptr;
             o.dir_th = d_ttheta ? d_ttheta + p0 : nullptr;
         }
-        st = launch_chain_kernel(*plan, d_r + p0, d_theta + p0, pc, with_dir ? 1 : 0, true, o, s);
+        st = launch_chain_kernel(*plan, d_r + p0, d_theta + p0, pc, with_dir ? 1 : 0, true, o, cs);
+        if (st != ZP_OK) return st;
+        st = pipeline.after_basis(chunk);
         if (st != ZP_OK) return st;
 
         GemmDesc g{};
@@ -649,10 +669,10 @@ extern "C" zp_status zp_series_jvp(const int32_t *h_n, const int32_t *h_m, int64
         g.epi = EPI_STORE;
         g.C = d_tf + p0 * B;
         g.ldc = B;
-        st = launch_gemm(g, s);
+        st = launch_gemm(g, cs);
         if (st != ZP_OK) return st;
     }
-    return ZP_OK;
+    return pipeline.finish();
 }
 
 // ------------------------------------------------------- second order --

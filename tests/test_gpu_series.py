@@ -107,7 +107,8 @@ def test_pipelined_forward(zp, oracle_mod, prec):
     256 compute units and 1024 sets: chunks of 4096 points for FP64 and FP32,
     8192 for bf16).  A ragged point count, with and without the cache: equal
     to the oracle, and bitwise equal to a forward that runs sequential chunks
-    (a small workspace budget turns the pipeline off)."""
+    (a small workspace budget turns the pipeline off); the same for the
+    forward-mode derivative."""
     rng = np.random.default_rng(12)
     n, m = W.ansi_modes(20)
     P, B = 20001, 1024
@@ -124,6 +125,12 @@ def test_pipelined_forward(zp, oracle_mod, prec):
         torch.cuda.synchronize()
         assert torch.equal(f, seq), (prec, cache is not None)
         assert _rel(f.cpu().numpy(), ref) <= TOL[prec]
+    # the forward-mode derivative pipelines its chunks the same way
+    tc, tr, tt = _dev(rng.standard_normal((n.size, B))), _dev(rng.standard_normal(P)), _dev(rng.standard_normal(P))
+    tf = zp.series_jvp(n, m, rd, td, cd, tc, tr, tt, prec=prec)
+    tf_seq = zp.series_jvp(n, m, rd, td, cd, tc, tr, tt, prec=prec, mem_budget=mn)
+    torch.cuda.synchronize()
+    assert torch.equal(tf, tf_seq), prec
 
 
 @pytest.mark.parametrize("M_n,P,B", [(0, 1, 1), (1, 1, 1), (3, 65, 3), (7, 129, 65), (10, 300, 130)])
