@@ -234,6 +234,7 @@ public:
     ChunkPipe(hipStream_t s, bool on) : s_(s), h_(on ? helper_stream() : nullptr) {}
     ~ChunkPipe()
     {
+        if (open_) (void)finish(); // an early return still joins the helper stream
         for (hipEvent_t e : ev_) (void)hipEventDestroy(e); // released once completed
     }
     ChunkPipe(const ChunkPipe &) = delete;
@@ -245,12 +246,15 @@ public:
     {
         hipEvent_t e = nullptr;
         zp_status st = on() ? record(s_, &e) : ZP_OK;
-        return e ? wait(h_, e) : st;
+        if (!e) return st;
+        open_ = true;
+        return wait(h_, e);
     }
     zp_status before_basis(int chunk) { return on() && prev_ ? wait(stream(chunk), prev_) : ZP_OK; }
     zp_status after_basis(int chunk) { return on() ? record(stream(chunk), &prev_) : ZP_OK; }
     zp_status finish()
     {
+        open_ = false;
         hipEvent_t e = nullptr;
         zp_status st = on() ? record(h_, &e) : ZP_OK;
         return e ? wait(s_, e) : st;
@@ -274,6 +278,7 @@ private:
 
     hipStream_t s_, h_;
     hipEvent_t prev_ = nullptr;
+    bool open_ = false;
     std::vector<hipEvent_t> ev_;
 };
 
