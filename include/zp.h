@@ -25,7 +25,12 @@
  *     each plane is the paper's (points x modes) output array in column-major
  *     order (Algorithms 1 and 2, "Output").
  *   - Every call is asynchronous on `stream` (a hipStream_t; NULL means the
- *     default stream).  All argument validation happens on the host before
+ *     default stream).  The series forward and forward-mode derivative may
+ *     run part of their work on one library-owned stream per device (default
+ *     priority, created on first use); it waits for `stream` through an event
+ *     at the start of the call, and `stream` waits for it before the call's
+ *     last piece of work, so to the caller the call is ordered on `stream`
+ *     alone.  All argument validation happens on the host before
  *     any device work: on error nothing is written and no kernel is launched.
  *     M == 0 or P == 0 (or B == 0 for the series) is a successful no-op.
  *   - The library allocates device memory only for its cached per-mode-list
