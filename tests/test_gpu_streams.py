@@ -79,6 +79,36 @@ def test_series_on_caller_stream(zp):
     assert torch.equal(out, ref)
 
 
+def test_pipelined_series_on_caller_stream(zp):
+    """A forward and a forward-mode derivative large enough to run their chunks
+    on the library's helper stream (20001 points x 1024 sets) stay ordered on
+    the caller's stream: queued behind the spin they return at once, and once
+    the caller's stream has finished their outputs are complete."""
+    n, m = W.ansi_modes(20)
+    r, th = W.disc_points(3, 20001)
+    rng = np.random.default_rng(4)
+    rd, td = torch.from_numpy(r).cuda(), torch.from_numpy(th).cuda()
+    c = torch.from_numpy(rng.standard_normal((n.size, 1024))).cuda()
+    tr = torch.from_numpy(rng.standard_normal(r.size)).cuda()
+    for prec in ("fp64", "bf16x3"):
+        ref = zp.series_forward(n, m, rd, td, c, prec)
+        ref_t = zp.series_jvp(n, m, rd, td, c, c, tr, None, prec=prec)
+        torch.cuda.synchronize()
+        out = torch.empty_like(ref)
+        out_t = torch.empty_like(ref_t)
+
+        def call():
+            out.copy_(zp.series_forward(n, m, rd, td, c, prec))
+            out_t.copy_(zp.series_jvp(n, m, rd, td, c, c, tr, None, prec=prec))
+
+        out_t.fill_(float("nan"))
+        dt, busy = _queued_behind_spin(call, out)
+        assert busy
+        assert dt < 0.05, f"the call blocked the host for {dt:.3f} s"
+        assert torch.equal(out, ref), prec
+        assert torch.equal(out_t, ref_t), prec
+
+
 def test_two_streams_concurrently(zp):
     """Two independent problems on two streams at once (shared plan cache):
     each equals its default-stream result."""
