@@ -497,7 +497,9 @@ zp_status zp_series_bwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
             ldz = CL.Pp;
             zsub = Mp * CL.Pp;
         } else {
-            st = basis_into(*plan, d_r, d_theta, p0, pc, ct, ws + L.z_off, ws + L.zr_off, ws + L.zt_off, pcp, Mp, M, s);
+            // the derivative planes only when dL/dr or dL/dtheta is wanted
+            st = basis_into(*plan, d_r, d_theta, p0, pc, ct, ws + L.z_off, need_rt ? ws + L.zr_off : nullptr,
+                            need_rt ? ws + L.zt_off : nullptr, pcp, Mp, M, s);
             if (st != ZP_OK) return st;
             z = ws + L.z_off;
             zr = ws + L.zr_off;
