@@ -67,6 +67,34 @@ def test_analysis_matches_oracle(zp, oracle_mod, prec, L, nr, nt, B):
     assert e <= TOL[prec]
 
 
+@pytest.fixture(scope="module")
+def full_ref(oracle_mod):
+    """The timed configuration: 2145 modes (n <= 64) from samples on a 256 x 512
+    grid (131072 points) for 1024 sets; the oracle forms every mode's
+    coefficient for 32 sampled sets, summing chunks of points (the transform
+    is linear in the samples)."""
+    n, m, r, th, w, f = _case(oracle_mod, 64, 256, 512, 1024, seed=65)
+    bs = np.sort(np.random.default_rng(66).choice(f.shape[1], 32, replace=False))
+    _say(f"[oracle] analysis modes={n.size} P={r.size} on {bs.size} sets")
+    acc = np.zeros((n.size, bs.size))
+    step = 16384
+    for p0 in range(0, r.size, step):
+        sl = slice(p0, p0 + step)
+        Z = oracle_mod.basis(n, m, r[sl], th[sl], oracle_mod.MASK_Z)[0]
+        acc += oracle_mod.analysis(Z, n, m, w[sl], f[sl][:, bs])
+    return (n, m, r, th, w, f), bs, acc
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp64"])
+def test_analysis_full_size_sampled(zp, full_ref, prec):
+    (n, m, r, th, w, f), bs, ref = full_ref
+    _say(f"analysis full size {prec}")
+    got = zp.series_analysis(n, m, _dev(r), _dev(th), _dev(w), _dev(f), prec).cpu().numpy()
+    e = _rel(got[:, bs], ref)
+    _say(f"  rel err {e:.2e}")
+    assert e <= TOL[prec]
+
+
 def test_analysis_any_rule(zp, oracle_mod):
     """Random disc points with equal weights (a Monte Carlo rule): not exact,
     but both sides compute the same sum."""

@@ -128,6 +128,47 @@ def test_bwd2_n40(zp, oracle_mod, prec):
         assert e <= TOL[prec], (k, e)
 
 
+@pytest.fixture(scope="module")
+def n64_bwd2_ref(oracle_mod):
+    """The timed configuration: 2145 modes, 65536 points, 1024 sets, with the
+    cotangents drawn as in the benchmark.  The oracle evaluates dL2/dg,
+    dL2/dr and dL2/dtheta on 256 sampled points (all sets; they are pointwise
+    in p), and dL2/dc on 32 sampled sets (all modes), summed over chunks of
+    points.  dL2/dc does not involve Z or the second-order planes, so those
+    chunks pass zeros for them."""
+    o = oracle_mod
+    wl = W.series_n64()
+    rng = np.random.default_rng(7)
+    uc = rng.standard_normal(wl.c.shape) / (wl.n + 1.0)[:, None]
+    ur, ut = rng.standard_normal(wl.P), rng.standard_normal(wl.P)
+    pick = np.random.default_rng(98)
+    ps = np.sort(pick.choice(wl.P, 256, replace=False))
+    bs = np.sort(pick.choice(wl.B, 32, replace=False))
+    _say(f"[oracle] bwd2 n64 on {ps.size} points and {bs.size} sets")
+    g_ref, _, r_ref, t_ref = _oracle(o, wl.n, wl.m, wl.r[ps], wl.theta[ps], wl.c, wl.g[ps], uc, ur[ps], ut[ps])
+    c_ref = np.zeros((wl.M, bs.size))
+    step = 8192
+    for p0 in range(0, wl.P, step):
+        sl = slice(p0, p0 + step)
+        Zr, Zt = o.basis(wl.n, wl.m, wl.r[sl], wl.theta[sl], o.MASK_DR | o.MASK_DTHETA)
+        zero = np.zeros_like(Zr)
+        c_ref += o.series_bwd2(zero, Zr, Zt, zero, zero, zero, wl.c[:, bs], wl.g[sl][:, bs], uc[:, bs], ur[sl],
+                               ut[sl])[1]
+    return wl, (uc, ur, ut), ps, bs, (g_ref, c_ref, r_ref, t_ref)
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp64"])
+def test_bwd2_n64_full_size_sampled(zp, n64_bwd2_ref, prec):
+    wl, (uc, ur, ut), ps, bs, (g_ref, c_ref, r_ref, t_ref) = n64_bwd2_ref
+    _say(f"[bwd2] n64 full size {prec}")
+    out_g, out_c, out_r, out_t = _gpu(zp, wl.n, wl.m, wl.r, wl.theta, wl.c, wl.g, uc, ur, ut, prec)
+    errs = {"out_g": _rel(out_g[ps], g_ref), "out_c": _rel(out_c[:, bs], c_ref), "out_r": _rel(out_r[ps], r_ref),
+            "out_t": _rel(out_t[ps], t_ref)}
+    _say(f"  {prec}:", {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, e in errs.items():
+        assert e <= TOL[prec], (k, e)
+
+
 def test_double_backward_gradgradcheck(zp):
     n, m = W.ansi_modes(5)
     rng = np.random.default_rng(34)
