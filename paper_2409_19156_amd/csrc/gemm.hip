@@ -467,9 +467,11 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc g)
 }
 
 // The same kernel compiled for four waves per SIMD (at most 128 registers), so
-// that two 512-thread workgroups share a CU.  Used where the body fits without
-// spilling: the FP64 forward (measured 6% faster; the other FP64 and FP32
-// instances would spill and lose more than they gain).
+// that two 512-thread workgroups share a CU and one's epilogue overlaps the
+// other's products.  Used for the FP64 forward (no spills; measured 6% faster)
+// and the FP64 column-dot (30 spilled registers, 4% faster: its epilogue reads
+// two 128 x 128 derivative tiles); the FP64 split-K (24 spilled registers, 11%
+// slower) and the FP32 and bf16 instances keep one workgroup per CU.
 template <int CT, int ALAY, int BLAY, int EPI>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void gemm_kernel_w4(GemmDesc g)
 {
@@ -482,7 +484,7 @@ hipError_t launch_t(const GemmDesc &g, hipStream_t s)
     using C = Cfg<CT>;
     const dim3 grid((unsigned)((g.M + C::BM - 1) / C::BM), (unsigned)((g.N + C::BN - 1) / C::BN),
                     (unsigned)g.splits);
-    if constexpr (CT == CT_F64 && EPI == EPI_STORE)
+    if constexpr (CT == CT_F64 && (EPI == EPI_STORE || EPI == EPI_COLDOT))
         hipLaunchKernelGGL((gemm_kernel_w4<CT, ALAY, BLAY, EPI>), grid, dim3(kThreads), 0, s, g);
     else
         hipLaunchKernelGGL((gemm_kernel<CT, ALAY, BLAY, EPI>), grid, dim3(kThreads), 0, s, g);
