@@ -88,9 +88,10 @@ def cpu_baseline(wl, sample_points: int):
 
 
 def series_leg(steps: int, warmup: int):
-    """FP64 vs mixed-precision Zernike series forward + backward on the n <= 64
-    workload (2145 modes, 65536 disc points, 1024 coefficient sets); the
-    mixed results' error is measured against the FP64 results."""
+    """FP64 vs mixed-precision Zernike series on the n <= 64 workload (2145
+    modes, 65536 disc points, 1024 coefficient sets): the forward alone, then
+    forward + backward; the mixed results' error is measured against the FP64
+    results."""
     import torch
 
     import paper_2409_19156_amd as zp
@@ -107,21 +108,30 @@ def series_leg(steps: int, warmup: int):
         ws = torch.empty(full, dtype=torch.uint8, device=dev)
         cache = torch.empty(cb, dtype=torch.uint8, device=dev)
 
-        def step():
+        res = []
+
+        def step():  # forward + backward; keeps the last outputs in res
             f = zp.series_forward(wl.n, wl.m, r, th, c, prec, cache=cache, ws=ws)
-            return (f,) + zp.series_backward(wl.n, wl.m, r, th, c, g, prec, cache=cache, ws=ws)
+            res[:] = (f,) + zp.series_backward(wl.n, wl.m, r, th, c, g, prec, cache=cache, ws=ws)
+
+        def fwd():
+            zp.series_forward(wl.n, wl.m, r, th, c, prec, cache=cache, ws=ws)
+
+        def timed(fn):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / steps
 
         for _ in range(warmup):
-            res = step()
+            step()
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(steps):
-            res = step()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
-        entry = {"ms_fwd_bwd": ms, "gemm_gflop": 3 * 2.0 * wl.P * wl.M * wl.B / 1e9}
+        ms_fwd = timed(fwd)
+        ms = timed(step)
+        entry = {"ms_fwd_bwd": ms, "ms_fwd": ms_fwd, "gemm_gflop": 3 * 2.0 * wl.P * wl.M * wl.B / 1e9}
         entry["algorithmic_tflops"] = entry["gemm_gflop"] / ms
         if prec == "fp64":
             ref = [x.clone() for x in res]
