@@ -115,8 +115,11 @@ __device__ __forceinline__ void kb_push(uint32_t (&w)[NW][4], double val, uint16
             }
         }
     } else {
+        // groups shared with another chain piece: the two workgroups write
+        // different bytes of the same 16-byte blocks; plain stores let L2
+        // merge them before the lines go to memory
 #pragma unroll
-        for (int q = 0; q < 3; ++q) __builtin_nontemporal_store(hv[q], kb + q * kb_sub + (eidx & 7));
+        for (int q = 0; q < 3; ++q) kb[q * kb_sub + (eidx & 7)] = hv[q];
     }
 }
 
