@@ -11,7 +11,8 @@
  * Polynomials are unnormalised, as in the paper.
  *
  * Conventions shared by every entry point
- *   - Pointers named h_* are host memory, d_* are device memory.  The caller
+ *   - Pointers named h_* are host memory, d_* are device memory of the
+ *     current HIP device, and `stream` belongs to that device.  The caller
  *     owns every buffer; the library only reads inputs and writes outputs.
  *   - Mode lists are host arrays (they are metadata, like shapes).  Duplicates
  *     are allowed: every column is written, in order (the paper's duplicated-
