@@ -24,7 +24,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 # Measured HBM traffic of the basis kernel on this workload: two rocprofv3
 # --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, median of 5) of
-#   bench.py --steps 3 --warmup 1 --no-series --no-spectral3d --no-radial --no-cpu-baseline
+#   bench.py --steps 3 --warmup 1 --no-series --no-spectral3d --no-radial --no-ad --no-cpu-baseline
 # scaled by what the same counters read for a plain 1 GiB device copy
 #   bench.py --copy-calibration-mb 1024
 # (FETCH_SIZE 524299.5 KiB for 1048576 KiB read: x2.0; WRITE_SIZE 1048576 KiB
@@ -305,8 +305,8 @@ def spectral3d_leg(steps: int, warmup: int):
 def main():
     args = _parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); multi-GPU runs are not part of this "
-              "build", file=sys.stderr)
+        print(f"bench.py measures a single GPU only (asked for --gpus {args.gpus}): the library runs one process "
+              "per GPU with no collectives", file=sys.stderr)
         sys.exit(2)
     import torch
 
