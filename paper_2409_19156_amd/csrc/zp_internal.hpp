@@ -37,7 +37,7 @@ namespace zp {
 // It is an exact algebraic rewrite of the paper's recurrence (the sum rule
 // of its coefficients makes v = 1 at s = 0 a fixed point), so the end point
 // is reproduced exactly and rounding errors vanish with s.
-constexpr int kSegEmits = 16; // emissions per chain piece
+constexpr int kSegEmits = 32; // emissions per chain piece
 
 struct Chain {
     int32_t alpha;    // |m| of every mode on this chain
