@@ -508,10 +508,15 @@ zp_status zp_series_bwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
             ldz = pcp;
             zsub = Mp * pcp;
         }
-        // g rows of this chunk: [pcp][Bp] (and [Bp][pcp] for bf16's grad_c operand)
-        void *gbuf = ws + L.g_off;
-        st = launch_convert(d_g + p0 * B, pc, B, B, ct, gbuf, Bp, pcp, pcp * Bp, false, s);
-        if (st != ZP_OK) return st;
+        // g rows of this chunk: [pcp][Bp] (and [Bp][pcp] for bf16's grad_c operand).
+        // In FP64, with B and the chunk already multiples of the pad, g itself
+        // has that layout and is read in place.
+        const bool g_in_place = ct == CT_F64 && B == Bp && pc == pcp && ((uintptr_t)d_g & 15) == 0;
+        const void *gbuf = g_in_place ? (const void *)(d_g + p0 * B) : (const void *)(ws + L.g_off);
+        if (!g_in_place) {
+            st = launch_convert(d_g + p0 * B, pc, B, B, ct, ws + L.g_off, Bp, pcp, pcp * Bp, false, s);
+            if (st != ZP_OK) return st;
+        }
         if (ct == CT_BF3 && d_grad_c) {
             st = launch_convert(d_g + p0 * B, pc, B, B, ct, ws + L.gt_off, pcp, Bp, Bp * pcp, true, s);
             if (st != ZP_OK) return st;
