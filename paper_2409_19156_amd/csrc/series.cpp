@@ -853,10 +853,14 @@ zp_status zp_series_bwd2(const int32_t *h_n, const int32_t *h_m, int64_t M, cons
         }
         st = launch_chain_kernel(*plan, d_r + p0, d_theta + p0, pc, run_e ? 2 : 1, true, o, s);
         if (st != ZP_OK) return st;
-        // the chunk's g: [pcp][Bp] (and [Bp][pcp] for the bf16 dL/dc operand)
-        void *gbuf = ws + L.g_off;
-        st = launch_convert(d_g + p0 * B, pc, B, B, ct, gbuf, Bp, pcp, pcp * Bp, false, s);
-        if (st != ZP_OK) return st;
+        // the chunk's g: [pcp][Bp] (and [Bp][pcp] for the bf16 dL/dc operand);
+        // read in place in FP64 when it already has that layout
+        const bool g_in_place = ct == CT_F64 && B == Bp && pc == pcp && ((uintptr_t)d_g & 15) == 0;
+        const void *gbuf = g_in_place ? (const void *)(d_g + p0 * B) : (const void *)(ws + L.g_off);
+        if (!g_in_place) {
+            st = launch_convert(d_g + p0 * B, pc, B, B, ct, ws + L.g_off, Bp, pcp, pcp * Bp, false, s);
+            if (st != ZP_OK) return st;
+        }
         if (run_c) {
             if (ct == CT_BF3) {
                 st = launch_convert(d_g + p0 * B, pc, B, B, ct, ws + L.gt_off, pcp, Bp, Bp * pcp, true, s);
