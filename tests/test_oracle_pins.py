@@ -107,11 +107,25 @@ def test_exact_rational_small_n(oracle_mod):
     assert worst <= 1e-28, worst
 
 
-@pytest.mark.parametrize("nmax", [200])
-def test_exact_integers_at_edge(oracle_mod, nmax):
+def _sparse_high_modes():
+    """A sparse set of modes up to the largest degree the library accepts
+    (n = 1000): every 25th m at n = 1000, 999, 998, 750 and 401, plus a few
+    small, middle and near-diagonal m (the modes the GPU parity test at
+    n = 1000 uses are among them)."""
+    ms = list(range(0, 1001, 25)) + [1, 2, 3, 250, 499, 500, 501, 997, 999]
+    modes = [(N, mm) for N in (1000, 999, 998, 750, 401) for mm in ms if mm <= N and (N - mm) % 2 == 0]
+    return np.array([a for a, _ in modes]), np.array([b for _, b in modes])
+
+
+def _mode_set(which):
+    return W.radial_pairs(200) if which == "n<=200" else _sparse_high_modes()
+
+
+@pytest.mark.parametrize("which", ["n<=200", "sparse n<=1000"])
+def test_exact_integers_at_edge(oracle_mod, which):
     """r = 1: R = 1 for every mode (P_K^{(alpha,0)}(-1) = (-1)^K), and each
     derivative is the exact integer sum_s coef_s (n-2s)_j (falling factorial)."""
-    n, m = W.radial_pairs(nmax)
+    n, m = _mode_set(which)
     hi, lo = oracle_mod.radial(n, m, [1.0], 3, with_lo=True)
     assert np.all(hi[0, :, 0] == 1.0)
     for i in range(n.size):
@@ -120,14 +134,14 @@ def test_exact_integers_at_edge(oracle_mod, nmax):
             got = X.as_fraction(hi[j, i, 0], lo[j, i, 0])
             assert abs(float(got - ref)) <= 1e-26 * max(1.0, abs(ref)), (n[i], m[i], j)
     # R'(1) = (n(n+2) - m^2)/2
-    for i in range(0, n.size, 37):
+    for i in range(0, n.size, 37 if n.size > 1000 else 1):
         assert hi[1, i, 0] == (n[i] * (n[i] + 2) - m[i] ** 2) / 2
 
 
-@pytest.mark.parametrize("nmax", [200])
-def test_exact_integers_at_centre(oracle_mod, nmax):
+@pytest.mark.parametrize("which", ["n<=200", "sparse n<=1000"])
+def test_exact_integers_at_centre(oracle_mod, which):
     """r = 0: d^j R = j! [r^j] R, nonzero only for j >= m, j = m mod 2."""
-    n, m = W.radial_pairs(nmax)
+    n, m = _mode_set(which)
     hi, lo = oracle_mod.radial(n, m, [0.0], 3, with_lo=True)
     for i in range(n.size):
         for j in range(4):
@@ -196,13 +210,15 @@ def test_zernike_recursion_identity(oracle_mod):
     assert checked > 9000
 
 
-@pytest.mark.parametrize("mm", [0, 1, 7, 50, 120, 199])
-def test_orthogonality_gauss_jacobi(oracle_mod, mm):
-    """int_0^1 R_n^m R_n'^m r dr = delta_nn' / (2(n+1)) for every n <= 200 of one
+@pytest.mark.parametrize("mm,nmax,tol", [(0, 200, 1e-11), (1, 200, 1e-11), (7, 200, 1e-11), (50, 200, 1e-11),
+                                         (120, 200, 1e-11), (199, 200, 1e-11), (0, 1000, 1e-9), (1, 1000, 1e-9),
+                                         (333, 1000, 1e-9), (998, 1000, 1e-9)])
+def test_orthogonality_gauss_jacobi(oracle_mod, mm, nmax, tol):
+    """int_0^1 R_n^m R_n'^m r dr = delta_nn' / (2(n+1)) for every n <= nmax of one
     m.  With x = 1 - 2r^2 the integral is 2^-(m+2) int (1-x)^m F(x) dx,
     F = R_n R_n' / r^(2m) a polynomial, done exactly by Gauss-Jacobi
     quadrature (alpha = m, beta = 0) from scipy."""
-    ns = np.arange(mm, 201, 2)
+    ns = np.arange(mm, nmax + 1, 2)
     K = (ns - mm) // 2
     N = int(K.max()) + 2
     x, w = roots_jacobi(N, mm, 0)
@@ -211,7 +227,9 @@ def test_orthogonality_gauss_jacobi(oracle_mod, mm):
     F = R / r[None, :] ** mm
     G = (F * w) @ F.T * 2.0 ** (-mm - 2)
     target = np.diag(1 / (2 * (ns + 1.0)))
-    assert np.abs(G - target).max() <= 1e-11 * (1 / (2 * (ns.max() + 1.0)))
+    # The Gram matrix is summed in float64 over N ~ K_max nodes: rounding grows with N (about 1e-10 of the
+    # smallest diagonal entry at n <= 1000); a wrong term gives O(1) deviations.
+    assert np.abs(G - target).max() <= tol * (1 / (2 * (ns.max() + 1.0)))
 
 
 def test_jacobi_chain_vs_mpmath(oracle_mod):
@@ -239,13 +257,15 @@ def test_jacobi_explicit_sum_vs_chain(oracle_mod):
                 assert abs((hi[k] - e_hi) + (lo[k] - e_lo)) <= 1e-28 * comb(k + max(a, b), k)
 
 
-@pytest.mark.parametrize("nm", [(200, 0), (200, 2), (199, 1), (200, 50), (200, 150), (201, 201), (180, 96)])
+@pytest.mark.parametrize("nm", [(200, 0), (200, 2), (199, 1), (200, 50), (200, 150), (201, 201), (180, 96),
+                                (1000, 0), (1000, 250), (1000, 500), (999, 1), (1000, 1000)])
 def test_high_n_derivatives_vs_mpmath(oracle_mod, nm):
-    """n ~ 200, derivative orders 0..3, against mpmath: (-1)^K r^m jacobi(K,m,0,1-2r^2)
-    differentiated numerically by mpmath.diff at 60 digits."""
+    """n ~ 200 and n ~ 1000 (the largest degree the library accepts), derivative
+    orders 0..3, against mpmath: (-1)^K r^m jacobi(K,m,0,1-2r^2) differentiated
+    numerically by mpmath.diff at 60 digits (80 above n = 200)."""
     n, m = nm
     K = (n - m) // 2
-    mpmath.mp.dps = 60
+    mpmath.mp.dps = 60 if n <= 200 else 80
     pts = [0.0312, 0.3, 0.70710678, 0.8123, 0.9999]
     hi, lo = oracle_mod.radial([n], [m], pts, 3, with_lo=True)
 

@@ -122,3 +122,131 @@ def test_second_order_adjoint(oracle_mod):
             else:
                 fd = (_l2(o, n, m, r, a, c, g, uc, ur, ut) - _l2(o, n, m, r, b2, c, g, uc, ur, ut)) / (2 * h)
             assert abs(fd - grad[p]) <= 1e-6 * (1 + abs(grad[p])), (p, fd, grad[p])
+
+
+# ---- the float64 contraction against exactly summed products -------------------
+#
+# The series oracle contracts its basis in float64 (BLAS).  The checks below
+# recompute sampled outputs as exact sums of products: every product of
+# doubles is expanded into an exact sum of doubles by Dekker's TwoProduct with
+# Veltkamp's splitting, and the pieces are added by math.fsum (Shewchuk's exact
+# summation, correctly rounded).  For the first-order outputs the basis enters
+# as the oracle's binary128 value (hi + lo), so rounding it to double is
+# covered too; the second-order outputs take the oracle's float64 planes as
+# given and check the contraction alone.
+
+import math  # noqa: E402
+from fractions import Fraction  # noqa: E402
+
+
+def _split(a):
+    t = 134217729.0 * a  # 2^27 + 1
+    hi = t - (t - a)
+    return hi, a - hi
+
+
+def _two_prod(a, b):
+    p = a * b
+    ah, al = _split(a)
+    bh, bl = _split(b)
+    return p, ((ah * bh - p) + ah * bl + al * bh) + al * bl
+
+
+def _exact_dot(pieces, *factors):
+    """sum_i (sum of pieces)[i] * prod_j factors[j][i] (all broadcast to one
+    shape), correctly rounded."""
+    shape = np.broadcast_shapes(*(np.shape(x) for x in (*pieces, *factors)))
+    pieces = [np.broadcast_to(p, shape) for p in pieces]
+    for f in factors:
+        nxt = []
+        for p in pieces:
+            a, b = _two_prod(p, np.broadcast_to(f, shape))
+            nxt += [a, b]
+        pieces = nxt
+    return math.fsum(np.concatenate([np.ravel(p) for p in pieces]).tolist())
+
+
+def test_exact_dot_helper_against_fractions():
+    rng = np.random.default_rng(3)
+    a, b, c = (rng.standard_normal(300) * 10.0 ** rng.integers(-8, 8, 300) for _ in range(3))
+    lo = a * 2.0 ** -60
+    exact = sum(Fraction(x) * Fraction(y) * Fraction(z) + Fraction(w) * Fraction(y) * Fraction(z)
+                for x, w, y, z in zip(a, lo, b, c))
+    assert _exact_dot([a, lo], b, c) == float(exact)
+
+
+def _rel_err(got, exact, norm):
+    return abs(got - exact) / norm
+
+
+def test_float64_series_reference_vs_exact_sums(oracle_mod):
+    """f, grad_c, grad_r, grad_theta of the oracle (n <= 40, 861 modes) at
+    sampled entries: within 1e-13 of the output's largest entry from the
+    exactly summed products over the binary128 basis (expected: a few units
+    of 1e-16; the GPU bar against this reference is 1e-12)."""
+    o = oracle_mod
+    rng = np.random.default_rng(23)
+    n, m = W.ansi_modes(40)
+    P, B = 48, 8
+    r, th = W.disc_points(23, P)
+    c = rng.standard_normal((n.size, B)) / (n + 1.0)[:, None]
+    g = rng.standard_normal((P, B))
+    hi, lo = o.basis(n, m, r, th, o.MASK_Z | o.MASK_DR | o.MASK_DTHETA, with_lo=True)
+    Z, Zr, Zt = hi
+    f = o.series_fwd(Z, c)
+    gc, gr, gt = o.series_bwd(Z, Zr, Zt, c, g)
+    worst = {}
+    nf = np.abs(f).max()
+    worst["f"] = max(_rel_err(f[p, b], _exact_dot([hi[0][:, p], lo[0][:, p]], c[:, b]), nf)
+                     for p, b in zip(rng.integers(0, P, 40), rng.integers(0, B, 40)))
+    nc = np.abs(gc).max()
+    worst["grad_c"] = max(_rel_err(gc[k, b], _exact_dot([hi[0][k], lo[0][k]], g[:, b]), nc)
+                          for k, b in zip(rng.integers(0, n.size, 40), rng.integers(0, B, 40)))
+    for name, q, grad in (("grad_r", 1, gr), ("grad_theta", 2, gt)):
+        nrm = np.abs(grad).max()
+        worst[name] = max(_rel_err(grad[p], _exact_dot([hi[q][:, p, None], lo[q][:, p, None]], c, g[p][None, :]), nrm)
+                          for p in range(0, P, 3))
+    assert max(worst.values()) <= 1e-13, worst
+
+
+def test_float64_second_order_contraction_vs_exact_sums(oracle_mod):
+    """The second-order adjoint (out_g, out_c, out_r, out_theta), n <= 24, at
+    sampled entries, against exactly summed products of the same float64
+    planes: within 1e-13 of each output's largest entry."""
+    o = oracle_mod
+    rng = np.random.default_rng(24)
+    n, m = W.ansi_modes(24)
+    P, B = 32, 6
+    r, th = W.disc_points(24, P)
+    c = rng.standard_normal((n.size, B)) / (n + 1.0)[:, None]
+    g = rng.standard_normal((P, B))
+    uc, ur, ut = rng.standard_normal(c.shape), rng.standard_normal(P), rng.standard_normal(P)
+    Z, Zr, Zt = o.series_basis(n, m, r, th)
+    Zrr, Zrt, Ztt = o.series_basis2(n, m, r, th)
+    og, oc, orr, ot = o.series_bwd2(Z, Zr, Zt, Zrr, Zrt, Ztt, c, g, uc, ur, ut)
+    one = lambda x: [np.asarray(x, dtype=np.float64)]  # noqa: E731
+    worst = {}
+    # out_g[p,b] = sum_k Z uc + ur sum_k Zr c + ut sum_k Zt c
+    nrm = np.abs(og).max()
+    worst["out_g"] = max(_rel_err(og[p, b], _exact_dot(one(np.concatenate([Z[:, p], Zr[:, p], Zt[:, p]])),
+                                                       np.concatenate([uc[:, b], c[:, b], c[:, b]]),
+                                                       np.concatenate([np.ones(n.size), np.full(n.size, ur[p]),
+                                                                       np.full(n.size, ut[p])])), nrm)
+                         for p, b in zip(rng.integers(0, P, 24), rng.integers(0, B, 24)))
+    # out_c[k,b] = sum_p (Zr ur + Zt ut)[k,p] g[p,b]
+    nrm = np.abs(oc).max()
+    worst["out_c"] = max(_rel_err(oc[k, b], _exact_dot(one(np.concatenate([Zr[k], Zt[k]])), np.concatenate([ur, ut]),
+                                                       np.concatenate([g[:, b], g[:, b]])), nrm)
+                         for k, b in zip(rng.integers(0, n.size, 24), rng.integers(0, B, 24)))
+    # out_r[p] = sum_k sum_b (Zr uc + ur Zrr c + ut Zrt c)[k] g[p,b]; out_t with (Zt, Zrt, Ztt)
+    for name, out, (A, Bp, Cp) in (("out_r", orr, (Zr, Zrr, Zrt)), ("out_theta", ot, (Zt, Zrt, Ztt))):
+        nrm = np.abs(out).max()
+        errs = []
+        for p in range(0, P, 4):
+            gp = g[p][None, :]
+            pieces = [np.concatenate([A[:, p, None], Bp[:, p, None], Cp[:, p, None]])]  # [3M, 1]
+            second = np.concatenate([uc, np.full_like(c, ur[p]), np.full_like(c, ut[p])])  # [3M, B]
+            third = np.concatenate([np.ones_like(c), c, c])
+            errs.append(_rel_err(out[p], _exact_dot(pieces, second, third, gp), nrm))
+        worst[name] = max(errs)
+    assert max(worst.values()) <= 1e-13, worst
