@@ -176,28 +176,58 @@ def test_series3d_autograd_matches_adjoint(zp, small):
         assert _rel(got.cpu().numpy(), exp) <= 1e-12, k
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
-def test_series3d_L32_full_size(zp, oracle_mod, prec):
-    """The benchmark workload (18 513 modes = 561 (n, m) pairs x 33 values of l,
-    32 768 polar points, 64 planes): f, grad_r, grad_theta on sampled points
-    against the oracle; grad_c and grad_phi through the adjoint identities
-    <grad_c, dc> = <g, f(dc)> (f is linear in c) and a central difference in phi."""
+def _oracle_all_points(o, w, chunk=1024):
+    """The oracle at every point, plane and mode of a large workload.  The basis
+    of mode j is the oracle basis of its pair (n_j, m_j), evaluated at every
+    point once per distinct pair; ``series3d_fwd`` / ``series3d_bwd`` then run
+    over consecutive chunks of the full (duplicated) mode list: grad_c of a
+    mode depends on that mode alone, and f, grad_r, grad_theta and grad_phi
+    are sums over modes, so the chunks' results add up."""
+    pairs, inv = np.unique(np.stack([w.n, w.m]), axis=1, return_inverse=True)
+    inv = inv.reshape(-1)
+    Zu, Zru, Ztu = o.series_basis(pairs[0], pairs[1], w.r, w.theta)
+    F, dF = o.fourier(w.l, w.phi), o.fourier(w.l, w.phi, 1)
+    P, Q, B = w.r.size, w.phi.size, w.c.shape[1]
+    f, gc = np.zeros((P, Q, B)), np.zeros(w.c.shape)
+    gr, gt, gp = np.zeros(P), np.zeros(P), np.zeros(Q)
+    for j0 in range(0, w.J, chunk):
+        sl = slice(j0, min(w.J, j0 + chunk))
+        u = inv[sl]
+        f += o.series3d_fwd(Zu[u], F[sl], w.c[sl])
+        a, b, c, d = o.series3d_bwd(Zu[u], Zru[u], Ztu[u], F[sl], dF[sl], w.c[sl], w.g)
+        gc[sl] = a
+        gr += b
+        gt += c
+        gp += d
+    return f, gc, gr, gt, gp
+
+
+@pytest.fixture(scope="module")
+def l32(oracle_mod):
     w = W.spectral3d_L32()
+    _say(f"series3d L32 oracle: J={w.J} P={w.r.size} Q={w.phi.size} (every point, plane and mode)")
+    return w, _oracle_all_points(oracle_mod, w)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_series3d_L32_full_size(zp, l32, prec):
+    """The benchmark workload (18 513 modes = 561 (n, m) pairs x 33 values of l,
+    32 768 polar points, 64 planes): every element of f, grad_c (all modes),
+    grad_r, grad_theta (all points) and grad_phi (all planes) against the
+    oracle; in addition, the adjoint identity <grad_c, dc> = <g, f(dc)> (f is
+    linear in c) and a central difference in phi."""
+    w, ref = l32
     P, Q, B = w.r.size, w.phi.size, w.c.shape[1]
     _say(f"series3d L32: J={w.J} P={P} Q={Q} B={B} prec={prec}")
-    rng = np.random.default_rng(9)
-    pts = np.sort(rng.choice(P, 48, replace=False))
-    pts[0], pts[-1] = 0, P - 1  # r = 0 and r = 1 rows of the grid
-    ref = _oracle(oracle_mod, w, pts)  # its grad_c / grad_phi cover only the sampled points: unused
-    f_ref, gr_ref, gt_ref = ref[0], ref[2], ref[3]
     got = _gpu(zp, w, prec)
-    errs = {"f": _rel(got[0][pts], f_ref), "grad_r": _rel(got[2][pts], gr_ref), "grad_theta": _rel(got[3][pts], gt_ref)}
-    _say("  sampled rel err", {k: f"{v:.2e}" for k, v in errs.items()})
+    errs = {k: _rel(a, b) for k, a, b in zip(NAMES, got, ref)}
+    _say("  rel err", {k: f"{v:.2e}" for k, v in errs.items()})
     for k, e in errs.items():
         assert e <= TOL[prec], (k, e)
+    rng = np.random.default_rng(9)
     # adjoint identity in c (FP64 forward of a random direction)
     dc = rng.standard_normal(w.c.shape)
-    r, th, ph, g = _dev(w.r), _dev(w.theta), _dev(w.phi), _dev(w.g)
+    r, th, ph = _dev(w.r), _dev(w.theta), _dev(w.phi)
     fd = zp.series3d_forward(w.n, w.m, w.l, r, th, ph, _dev(dc), "fp64").cpu().numpy()
     lhs, rhs = float(np.sum(got[1] * dc)), float(np.sum(w.g * fd))
     assert abs(lhs - rhs) <= TOL[prec] * np.abs(got[1]).sum() * np.abs(dc).max(), (lhs, rhs)

@@ -116,6 +116,28 @@ def test_bwd2_chunked_workspace(zp, case12):
         assert _rel(a, b) <= 1e-12, k
 
 
+def test_bwd2_fp64_chunks_read_g_in_place(zp, oracle_mod):
+    """FP64 with 128 sets and the smallest workspace: chunks of 128 points read
+    their rows of g in place at offset p0 > 0; the ragged last chunk (100
+    points) goes through the padded copy.  Against the oracle."""
+    import ctypes
+
+    from paper_2409_19156_amd import _lib
+
+    P, B = 12 * 128 + 100, 128
+    args = _case(16, P, B, seed=42)
+    n = args[0]
+    full, mn = ctypes.c_size_t(), ctypes.c_size_t()
+    assert _lib.load().zp_series_bwd2_workspace(n.size, P, B, 0, ctypes.byref(full), ctypes.byref(mn)) == 0
+    assert mn.value < full.value
+    ws = torch.empty(mn.value, dtype=torch.uint8, device="cuda")
+    _say(f"bwd2 fp64 in-place g chunks: M={n.size} P={P} B={B} ws={mn.value}")
+    got = _gpu(zp, *args, "fp64", ws=ws)
+    ref = _oracle(oracle_mod, *args)
+    for k, a, b in zip(NAMES, got, ref):
+        assert _rel(a, b) <= 1e-12, k
+
+
 @pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
 def test_bwd2_n40(zp, oracle_mod, prec):
     """861 modes, 4096 points, 64 sets."""
