@@ -297,7 +297,9 @@ zp_status zp_series3d_bwd(const int32_t *h_n, const int32_t *h_m, const int32_t 
  * and data that is a series in those modes, nr >= ceil((L + 1) / 2) and
  * nt >= 2 L + 1 make the transform exact.
  *   h_r, h_theta, h_w  host double[nr * nt] (outputs); weights sum to pi.
- * Errors: ZP_ERR_ARG (nr or nt < 1, nr > 2^20, nt > 2^24, null pointer).
+ * The rule costs O(nr^2) host operations (Newton's method on each node);
+ * nr <= 4096 covers every degree the library accepts (n <= 1000 needs 501).
+ * Errors: ZP_ERR_ARG (nr or nt < 1, nr > 4096, nt > 2^24, null pointer).
  */
 zp_status zp_analysis_grid(int64_t nr, int64_t nt, double *h_r, double *h_theta, double *h_w);
 

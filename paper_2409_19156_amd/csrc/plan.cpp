@@ -3,6 +3,7 @@
 // its alpha), per-step coefficients, and a small device-side cache.
 #include <algorithm>
 #include <cstdlib>
+#include <iterator>
 #include <list>
 #include <mutex>
 
@@ -207,30 +208,15 @@ zp_status get_zrec_table(Plan &plan)
 
 Plan::~Plan()
 {
-    if (d_zrec) {
-        int cur = -1;
-        (void)hipGetDevice(&cur);
-        (void)hipSetDevice(device);
-        (void)hipDeviceSynchronize();
-        (void)hipFree(d_zrec);
-        if (cur >= 0) (void)hipSetDevice(cur);
-    }
-    if (d_direct) {
-        int cur = -1;
-        (void)hipGetDevice(&cur);
-        (void)hipSetDevice(device);
-        (void)hipDeviceSynchronize();
-        (void)hipFree(d_direct);
-        if (cur >= 0) (void)hipSetDevice(cur);
-    }
-    if (dmem) {
-        int cur = -1;
-        (void)hipGetDevice(&cur);
-        (void)hipSetDevice(device);
-        (void)hipDeviceSynchronize(); // kernels may still read the tables
-        (void)hipFree(dmem);
-        if (cur >= 0) (void)hipSetDevice(cur);
-    }
+    if (!dmem && !d_direct && !d_zrec) return;
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(device);
+    (void)hipDeviceSynchronize(); // kernels may still read the tables
+    if (d_zrec) (void)hipFree(d_zrec);
+    if (d_direct) (void)hipFree(d_direct);
+    if (dmem) (void)hipFree(dmem);
+    if (cur >= 0) (void)hipSetDevice(cur);
 }
 
 static zp_status upload(Plan &p)
@@ -283,28 +269,49 @@ size_t cache_capacity()
 }
 } // namespace
 
+// Looks the mode list up under the cache lock.  A missing plan is built and
+// uploaded without the lock (a plan of the same list built meanwhile by another
+// thread wins), and plans pushed out of the cache are released after the lock
+// is dropped: releasing one synchronizes its device, since kernels may still
+// read its tables.
 zp_status get_plan(const int32_t *n, const int32_t *m, int64_t M, std::shared_ptr<Plan> *out)
 {
     int dev = 0;
     zp_status st = hip_check(hipGetDevice(&dev), "hipGetDevice");
     if (st != ZP_OK) return st;
-    std::lock_guard<std::mutex> lock(g_mu);
-    for (auto it = g_cache.begin(); it != g_cache.end(); ++it) {
-        Plan &p = **it;
-        if (p.device == dev && (int64_t)p.n.size() == M && std::equal(p.n.begin(), p.n.end(), n) &&
-            std::equal(p.m.begin(), p.m.end(), m)) {
-            g_cache.splice(g_cache.begin(), g_cache, it);
-            *out = g_cache.front();
-            return ZP_OK;
+    auto same = [&](const Plan &p) {
+        return p.device == dev && (int64_t)p.n.size() == M && std::equal(p.n.begin(), p.n.end(), n) &&
+               std::equal(p.m.begin(), p.m.end(), m);
+    };
+    auto lookup = [&]() -> bool { // under the lock
+        for (auto it = g_cache.begin(); it != g_cache.end(); ++it) {
+            if (same(**it)) {
+                g_cache.splice(g_cache.begin(), g_cache, it);
+                *out = g_cache.front();
+                return true;
+            }
         }
+        return false;
+    };
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        if (lookup()) return ZP_OK;
     }
-    auto plan = build_plan_host(n, m, M);
+    std::shared_ptr<Plan> plan = build_plan_host(n, m, M);
     plan->device = dev;
     st = upload(*plan);
     if (st != ZP_OK) return st;
-    g_cache.push_front(plan);
-    while (g_cache.size() > cache_capacity()) g_cache.pop_back();
-    *out = plan;
+    std::list<std::shared_ptr<Plan>> released; // destroyed after the lock below
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        if (lookup()) {
+            released.push_back(std::move(plan));
+        } else {
+            g_cache.push_front(plan);
+            *out = plan;
+            while (g_cache.size() > cache_capacity()) released.splice(released.end(), g_cache, std::prev(g_cache.end()));
+        }
+    }
     return ZP_OK;
 }
 

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <iterator>
 #include <list>
 #include <mutex>
 #include <unordered_map>
@@ -107,20 +108,28 @@ zp_status upload3(Plan3 &p)
 
 } // namespace
 
+// As get_plan: the lookup under the lock, a missing plan built without it,
+// and plans pushed out of the cache released after the lock is dropped.
 zp_status get_plan3(const int32_t *n, const int32_t *m, const int32_t *l, int64_t J, std::shared_ptr<Plan3> *out)
 {
     int dev = 0;
     zp_status st = hip_check(hipGetDevice(&dev), "hipGetDevice");
     if (st != ZP_OK) return st;
-    std::lock_guard<std::mutex> lock(g_mu3);
-    for (auto it = g_cache3.begin(); it != g_cache3.end(); ++it) {
-        Plan3 &p = **it;
-        if (p.device == dev && (int64_t)p.n.size() == J && std::equal(p.n.begin(), p.n.end(), n) &&
-            std::equal(p.m.begin(), p.m.end(), m) && std::equal(p.l.begin(), p.l.end(), l)) {
-            g_cache3.splice(g_cache3.begin(), g_cache3, it);
-            *out = g_cache3.front();
-            return ZP_OK;
+    auto lookup = [&]() -> bool { // under the lock
+        for (auto it = g_cache3.begin(); it != g_cache3.end(); ++it) {
+            Plan3 &p = **it;
+            if (p.device == dev && (int64_t)p.n.size() == J && std::equal(p.n.begin(), p.n.end(), n) &&
+                std::equal(p.m.begin(), p.m.end(), m) && std::equal(p.l.begin(), p.l.end(), l)) {
+                g_cache3.splice(g_cache3.begin(), g_cache3, it);
+                *out = g_cache3.front();
+                return true;
+            }
         }
+        return false;
+    };
+    {
+        std::lock_guard<std::mutex> lock(g_mu3);
+        if (lookup()) return ZP_OK;
     }
     auto p = std::make_shared<Plan3>();
     p->n.assign(n, n + J);
@@ -130,9 +139,17 @@ zp_status get_plan3(const int32_t *n, const int32_t *m, const int32_t *l, int64_
     p->device = dev;
     st = upload3(*p);
     if (st != ZP_OK) return st;
-    g_cache3.push_front(p);
-    while (g_cache3.size() > capacity3()) g_cache3.pop_back();
-    *out = p;
+    std::list<std::shared_ptr<Plan3>> released; // destroyed after the lock below
+    {
+        std::lock_guard<std::mutex> lock(g_mu3);
+        if (lookup()) {
+            released.push_back(std::move(p));
+        } else {
+            g_cache3.push_front(p);
+            *out = p;
+            while (g_cache3.size() > capacity3()) released.splice(released.end(), g_cache3, std::prev(g_cache3.end()));
+        }
+    }
     return ZP_OK;
 }
 

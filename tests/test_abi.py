@@ -202,6 +202,20 @@ def test_analysis_grid_matches_oracle_rule(oracle_mod):
         assert abs(w.sum() - np.pi) <= 1e-13
 
 
+def test_analysis_grid_largest_rule_is_fast():
+    """The largest accepted rule (4096 radial nodes) is built in well under a
+    second of host time; its weights still sum to the disc's area."""
+    import time
+
+    import paper_2409_19156_amd as zp
+
+    t0 = time.perf_counter()
+    r, _, w = zp.analysis_grid(4096, 1)
+    assert time.perf_counter() - t0 < 5.0
+    assert np.all(np.diff(r) > 0) and 0 < r[0] and r[-1] < 1
+    assert abs(w.sum() - np.pi) <= 1e-12
+
+
 def test_analysis_validation(lib):
     n, m = _modes([2, 3], [0, -1])
     nd, md = n.ctypes.data, m.ctypes.data
@@ -209,6 +223,7 @@ def test_analysis_validation(lib):
     p = buf.ctypes.data
     assert lib.zp_analysis_grid(0, 4, p, p, p) == ERR_ARG
     assert lib.zp_analysis_grid(2, 4, None, p, p) == ERR_ARG
+    assert lib.zp_analysis_grid(4097, 1, p, p, p) == ERR_ARG  # above the radial node limit (O(nr^2) host work)
     full, mn = ctypes.c_size_t(), ctypes.c_size_t()
     assert lib.zp_series_analysis_workspace(2, 100, 3, 2, ctypes.byref(full), ctypes.byref(mn)) == OK
     assert 0 < mn.value <= full.value
