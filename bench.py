@@ -21,6 +21,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+FP64_PEAK_TFS = 78.6  # MI355X FP64 MFMA (dense), published
 
 # Measured HBM traffic of the basis kernel on this workload: two rocprofv3
 # --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, median of 5) of
@@ -66,9 +67,22 @@ def _parse():
     return ap.parse_args()
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(wl, sample_points: int):
     """The oracle (quad precision, OpenMP over points), untuned, on a bounded
-    sample of the same workload's points; scaled to entries/s."""
+    sample of the same workload's points; scaled to entries/s.  Timed with all
+    the threads OpenMP gives it (the reported value) and with one thread on a
+    smaller strided sample."""
     import oracle
 
     oracle.build(force=False)
@@ -82,16 +96,63 @@ def cpu_baseline(wl, sample_points: int):
     oracle.basis(wl.n, wl.m, wl.r[idx], wl.theta[idx], wl.mask)
     dt = time.perf_counter() - t0
     entries = wl.M * 5 * sample_points
+    one = max(1, sample_points // 8)
+    idx1 = np.linspace(0, wl.P - 1, one).astype(np.int64)
+    t0 = time.perf_counter()
+    oracle.basis(wl.n, wl.m, wl.r[idx1], wl.theta[idx1], wl.mask, nthreads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": entries / dt, "unit": "entries/s", "cores": threads, "kind": "oracle",
             "sample": f"{sample_points} of {wl.P} grid points (evenly strided), all {wl.M} modes, 5 outputs; "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s",
+            "single_thread": {"value": wl.M * 5 * one / dt1, "unit": "entries/s", "cores": 1,
+                              "sample": f"{one} of {wl.P} grid points (evenly strided); {dt1:.1f} s"},
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
+
+
+def _errors(got, ref):
+    """Error measures of one output tensor against the oracle: max-norm and
+    Frobenius-norm relative errors, and the largest elementwise relative error
+    over the entries whose magnitude exceeds 1e-3 of the largest."""
+    got, ref = np.asarray(got, dtype=np.float64), np.asarray(ref, dtype=np.float64)
+    d = np.abs(got - ref)
+    big = np.abs(ref) > 1e-3 * np.abs(ref).max()
+    return {"inf": float(d.max() / np.abs(ref).max()),
+            "fro": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+            "elem": float((d[big] / np.abs(ref[big])).max())}
+
+
+def _oracle_sample(name: str, wl):
+    """The oracle's values on a fixed sample of a series workload, written by
+    tests/golden/make_series_refs.py (the benchmark does not run the oracle
+    outside its CPU-baseline leg).  None if the file is missing or was made
+    from other inputs."""
+    import hashlib
+
+    path = os.path.join(ROOT, "tests", "golden", name)
+    if not os.path.exists(path):
+        return None
+    d = np.load(path, allow_pickle=False)
+    h = hashlib.sha256()
+    for a in (wl.n, wl.m, wl.r, wl.theta, wl.c, wl.g):
+        h.update(np.ascontiguousarray(a).tobytes())
+    if str(d["digest"]) != h.hexdigest():
+        return None
+    return {k: d[k] for k in d.files}
+
+
+def _sample_errors(ref, f, gc, gr, gt):
+    """Errors of the GPU outputs (numpy) on the stored oracle sample."""
+    ps = ref["ps"]
+    got = (f[ps][:, ref["bs_f"]], gc[:, ref["bs_c"]], gr[ps], gt[ps])
+    return {k: _errors(a, ref[k]) for k, a in zip(("f", "grad_c", "grad_r", "grad_theta"), got)}
 
 
 def series_leg(steps: int, warmup: int):
     """FP64 vs mixed-precision Zernike series on the n <= 64 workload (2145
     modes, 65536 disc points, 1024 coefficient sets): the forward alone, then
-    forward + backward; the mixed results' error is measured against the FP64
-    results."""
+    forward + backward; each precision's error per output against the oracle
+    on a fixed sample (f on 128 points x 64 sets, grad_r and grad_theta on the
+    128 points, grad_c for all modes on 8 sets)."""
     import torch
 
     import paper_2409_19156_amd as zp
@@ -101,8 +162,9 @@ def series_leg(steps: int, warmup: int):
     dev = torch.device("cuda:0")
     r, th = torch.from_numpy(wl.r).to(dev), torch.from_numpy(wl.theta).to(dev)
     c, g = torch.from_numpy(wl.c).to(dev), torch.from_numpy(wl.g).to(dev)
-    out, ref = {}, None
+    out = {}
     stream = torch.cuda.current_stream(dev)
+    oref = _oracle_sample("series_n64_oracle_sample.npz", wl)
     for prec in ("fp64", "fp32", "bf16x3"):
         full, _, cb = zp.series_sizes(wl.M, wl.P, wl.B, prec)
         ws = torch.empty(full, dtype=torch.uint8, device=dev)
@@ -133,18 +195,61 @@ def series_leg(steps: int, warmup: int):
         ms = timed(step)
         entry = {"ms_fwd_bwd": ms, "ms_fwd": ms_fwd, "gemm_gflop": 3 * 2.0 * wl.P * wl.M * wl.B / 1e9}
         entry["algorithmic_tflops"] = entry["gemm_gflop"] / ms
-        if prec == "fp64":
-            ref = [x.clone() for x in res]
-        else:
-            errs = [((a - b).abs().max() / b.abs().max()).item() for a, b in zip(res, ref)]
-            entry["rel_err_vs_fp64"] = dict(zip(("f", "grad_c", "grad_r", "grad_theta"), errs))
+        if oref is not None:
+            entry["err_vs_oracle"] = _sample_errors(oref, *(x.cpu().numpy() for x in res))
         out[prec] = entry
         del ws, cache
         torch.cuda.empty_cache()
     out["speedup_bf16x3_vs_fp64"] = out["fp64"]["ms_fwd_bwd"] / out["bf16x3"]["ms_fwd_bwd"]
     out["speedup_fp32_vs_fp64"] = out["fp64"]["ms_fwd_bwd"] / out["fp32"]["ms_fwd_bwd"]
     out["workload"] = "series_n64: ANSI n<=64 (2145 modes), 65536 disc points, 1024 sets, fwd+bwd (c, r, theta)"
+    out["err_sample"] = ("oracle (stored) on 128 fixed points x 64 sets (f), the same points (grad_r, grad_theta), "
+                         "8 sets x all modes (grad_c)" if oref is not None else "oracle sample missing")
     return out
+
+
+def series_n40_leg(steps: int, warmup: int):
+    """The FP64 differentiable series on the n <= 40 workload (861 modes, 16384
+    disc points, 256 sets): forward + backward through the autograd function,
+    with the contraction work (three GEMMs of 2PMB) as a fraction of the FP64
+    MFMA peak, and the error of every output against the oracle on a fixed
+    sample (f on 256 points x 64 sets, grad_r and grad_theta on the 256
+    points, grad_c for all modes on 16 sets)."""
+    import torch
+
+    import paper_2409_19156_amd as zp
+    import zp_workloads as W
+
+    wl = W.series_n40()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    r0, th0 = torch.from_numpy(wl.r).to(dev), torch.from_numpy(wl.theta).to(dev)
+    c0, g = torch.from_numpy(wl.c).to(dev), torch.from_numpy(wl.g).to(dev)
+    res = []
+
+    def step():
+        c, r, th = (x.detach().requires_grad_() for x in (c0, r0, th0))
+        f = zp.series(c, r, th, wl.n, wl.m, "fp64")
+        f.backward(g)
+        res[:] = (f.detach(), c.grad, r.grad, th.grad)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    gflop = 3 * 2.0 * wl.P * wl.M * wl.B / 1e9
+    oref = _oracle_sample("series_n40_oracle_sample.npz", wl)
+    errs = _sample_errors(oref, *(x.cpu().numpy() for x in res)) if oref is not None else "oracle sample missing"
+    return {"workload": "series_n40: ANSI n<=40 (861 modes), 16384 disc points, 256 sets, FP64, forward + "
+                        "autograd backward (c, r, theta)",
+            "ms_fwd_bwd": ms, "gemm_gflop": gflop, "algorithmic_tflops": gflop / ms,
+            "frac_of_fp64_mfma_peak": gflop / ms / FP64_PEAK_TFS, "err_vs_oracle": errs}
 
 
 def radial_legs(steps: int, warmup: int):
@@ -389,6 +494,7 @@ def main():
     }
     if not args.no_series:
         res["series"] = series_leg(steps=max(3, min(args.steps, 10)), warmup=2)
+        res["series_n40"] = series_n40_leg(steps=max(3, min(args.steps, 20)), warmup=3)
     if not args.no_spectral3d:
         res["spectral3d"] = spectral3d_leg(steps=max(3, min(args.steps, 10)), warmup=2)
     if not args.no_radial:
