@@ -35,7 +35,8 @@
  *     any device work: on error nothing is written and no kernel is launched.
  *     M == 0 or P == 0 (or B == 0 for the series) is a successful no-op.
  *   - The library allocates device memory only for its cached per-mode-list
- *     tables ("plans"), which zp_cache_clear() releases.  Calls from several
+ *     tables ("plans"), which zp_cache_clear() releases, and holds one fixed
+ *     array per GPU for zp_series_fwd_noalloc.  Calls from several
  *     host threads are safe; calls that write the same buffers race, as any
  *     asynchronous work does.
  */
@@ -320,6 +321,27 @@ zp_status zp_series_analysis_workspace(int64_t M, int64_t P, int64_t B, int32_t 
 zp_status zp_series_analysis(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r,
                              const double *d_theta, const double *d_w, int64_t P, const double *d_f, int64_t B,
                              int32_t prec, double *d_c, void *d_ws, size_t ws_bytes, void *stream);
+
+/*
+ * zp_series_fwd_noalloc -- zp_series_fwd (no basis cache) for callers that
+ * cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  It calls no hipMalloc / hipFree
+ * and creates no stream or event; its workspace and its plan tables live in a
+ * fixed device array of ZP_NOALLOC_SCRATCH_BYTES per GPU, which the library
+ * holds until the process ends.  Work runs on `stream` alone, in chunks of
+ * points that fit the array.
+ *   Arguments and output as zp_series_fwd.
+ *   A call whose mode list differs from the previous call's on this GPU
+ *   copies the new tables into the array and waits for `stream` once.
+ *   Every call on a GPU shares that GPU's array: calls that overlap on one
+ *   GPU (on other streams, or from host threads without ordering) race.
+ * Errors: as zp_series_fwd; ZP_ERR_WORKSPACE when the tables plus the
+ * smallest workspace (one 128-point chunk) exceed ZP_NOALLOC_SCRATCH_BYTES.
+ */
+#define ZP_NOALLOC_SCRATCH_BYTES (64u << 20)
+zp_status zp_series_fwd_noalloc(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r,
+                                const double *d_theta, int64_t P, const double *d_c, int64_t B, int32_t prec,
+                                double *d_f, void *stream);
 
 /* Static description of a status code. */
 const char *zp_status_string(zp_status s);

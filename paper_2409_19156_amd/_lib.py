@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "ZP_OK", 1: "ZP_ERR_MODE", 2: "ZP_ERR_ARG", 3: "ZP_ERR_ORDER"
 EXPORTS = ("zp_radial", "zp_radial_direct", "zp_radial_zernike_recursion", "zp_basis", "zp_series_workspace", "zp_series_cache_bytes", "zp_series_fwd",
            "zp_series_bwd", "zp_series_jvp", "zp_series_bwd2_workspace", "zp_series_bwd2", "zp_series3d_workspace",
            "zp_series3d_cache_bytes", "zp_series3d_fwd", "zp_series3d_bwd", "zp_analysis_grid",
-           "zp_series_analysis_workspace", "zp_series_analysis", "zp_status_string", "zp_last_error", "zp_cache_clear",
+           "zp_series_analysis_workspace", "zp_series_analysis", "zp_series_fwd_noalloc", "zp_status_string", "zp_last_error", "zp_cache_clear",
            "zp_abi_version")
 
 
@@ -61,6 +61,7 @@ def load() -> ctypes.CDLL:
         "zp_analysis_grid": [i64, i64, vp, vp, vp],
         "zp_series_analysis_workspace": [i64, i64, i64, i32, szp, szp],
         "zp_series_analysis": [vp, vp, i64, vp, vp, vp, i64, vp, i64, i32, vp, vp, sz, vp],
+        "zp_series_fwd_noalloc": [vp, vp, i64, vp, vp, i64, vp, i64, i32, vp, vp],
     }
     for name, args in sig.items():
         if not hasattr(lib, name):

@@ -219,36 +219,53 @@ Plan::~Plan()
     if (cur >= 0) (void)hipSetDevice(cur);
 }
 
-static zp_status upload(Plan &p)
+// Device image of a plan's tables: chains and pieces side by side, then the
+// coefficients, the emissions and the permutation, each 256-byte aligned.
+size_t plan_image(const Plan &p, std::vector<unsigned char> *host, PlanOffsets *o)
 {
-    // chains and pieces side by side
-    std::vector<Chain> both(p.chains);
-    both.insert(both.end(), p.pieces.begin(), p.pieces.end());
-    const size_t a = both.size() * sizeof(Chain);
+    const size_t a = (p.chains.size() + p.pieces.size()) * sizeof(Chain);
     const size_t b = std::max<size_t>(p.coefs.size(), 1) * sizeof(Coef);
     const size_t c = p.emits.size() * sizeof(Emit);
     const size_t d = p.emits.size() * sizeof(int32_t);
-    const size_t off_b = (a + 255) / 256 * 256;
-    const size_t off_c = off_b + (b + 255) / 256 * 256;
-    const size_t off_d = off_c + (c + 255) / 256 * 256;
-    const size_t total = off_d + d;
-    std::vector<unsigned char> host(total, 0);
-    std::copy_n((const unsigned char *)both.data(), a, host.data());
-    if (!p.coefs.empty()) std::copy_n((const unsigned char *)p.coefs.data(), p.coefs.size() * sizeof(Coef), host.data() + off_b);
-    std::copy_n((const unsigned char *)p.emits.data(), c, host.data() + off_c);
+    o->coefs = (a + 255) / 256 * 256;
+    o->emits = o->coefs + (b + 255) / 256 * 256;
+    o->perm = o->emits + (c + 255) / 256 * 256;
+    o->total = o->perm + d;
+    if (!host) return o->total;
+    host->assign(o->total, 0);
+    unsigned char *h = host->data();
+    std::copy_n((const unsigned char *)p.chains.data(), p.chains.size() * sizeof(Chain), h);
+    std::copy_n((const unsigned char *)p.pieces.data(), p.pieces.size() * sizeof(Chain),
+                h + p.chains.size() * sizeof(Chain));
+    if (!p.coefs.empty()) std::copy_n((const unsigned char *)p.coefs.data(), p.coefs.size() * sizeof(Coef), h + o->coefs);
+    std::copy_n((const unsigned char *)p.emits.data(), c, h + o->emits);
     for (size_t e = 0; e < p.emits.size(); ++e) {
         const int32_t col = p.emits[e].col;
-        std::copy_n((const unsigned char *)&col, sizeof col, host.data() + off_d + e * sizeof(int32_t));
+        std::copy_n((const unsigned char *)&col, sizeof col, h + o->perm + e * sizeof(int32_t));
     }
-    zp_status st = hip_check(hipMalloc(&p.dmem, total), "hipMalloc(plan)");
-    if (st != ZP_OK) return st;
-    st = hip_check(hipMemcpy(p.dmem, host.data(), total, hipMemcpyHostToDevice), "hipMemcpy(plan)");
-    if (st != ZP_OK) return st;
-    p.d_chains = (const Chain *)p.dmem;
+    return o->total;
+}
+
+void plan_bind(Plan &p, const void *base, const PlanOffsets &o)
+{
+    const unsigned char *b = (const unsigned char *)base;
+    p.d_chains = (const Chain *)b;
     p.d_pieces = p.d_chains + p.chains.size();
-    p.d_coefs = (const Coef *)((unsigned char *)p.dmem + off_b);
-    p.d_emits = (const Emit *)((unsigned char *)p.dmem + off_c);
-    p.d_perm = (const int32_t *)((unsigned char *)p.dmem + off_d);
+    p.d_coefs = (const Coef *)(b + o.coefs);
+    p.d_emits = (const Emit *)(b + o.emits);
+    p.d_perm = (const int32_t *)(b + o.perm);
+}
+
+static zp_status upload(Plan &p)
+{
+    std::vector<unsigned char> host;
+    PlanOffsets o;
+    plan_image(p, &host, &o);
+    zp_status st = hip_check(hipMalloc(&p.dmem, o.total), "hipMalloc(plan)");
+    if (st != ZP_OK) return st;
+    st = hip_check(hipMemcpy(p.dmem, host.data(), o.total, hipMemcpyHostToDevice), "hipMemcpy(plan)");
+    if (st != ZP_OK) return st;
+    plan_bind(p, p.dmem, o);
     return ZP_OK;
 }
 

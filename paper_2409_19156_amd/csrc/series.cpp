@@ -329,31 +329,43 @@ zp_status zp_series_workspace(int64_t M, int64_t P, int64_t B, int32_t prec, siz
     return ZP_OK;
 }
 
-zp_status zp_series_fwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r, const double *d_theta,
-                        int64_t P, const double *d_c, int64_t B, int32_t prec, double *d_f, void *d_cache, void *d_ws,
-                        size_t ws_bytes, void *stream)
+} // extern "C"
+
+namespace zp {
+
+zp_status series_fwd_checks(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r,
+                            const double *d_theta, int64_t P, const double *d_c, int64_t B, int32_t prec,
+                            const double *d_f)
 {
     zp_status st = common_checks(h_n, h_m, M, P, B, prec);
     if (st != ZP_OK) return st;
     if (M == 0 || P == 0 || B == 0) return ZP_OK;
     if (!d_r || !d_theta || !d_c || !d_f) return set_error(ZP_ERR_ARG, "null pointer");
-    if (!d_ws || ((uintptr_t)d_ws & 255)) return set_error(ZP_ERR_ARG, "workspace must be non-null and 256-byte aligned");
-    if ((uintptr_t)d_cache & 255) return set_error(ZP_ERR_ARG, "cache must be 256-byte aligned");
+    return ZP_OK;
+}
+
+size_t series_fwd_min_ws(int64_t M, int64_t P, int64_t B, int32_t prec)
+{
+    return WsLayout(M, std::min<int64_t>(P, kPad), B, ct_of(prec), true, false, false).total;
+}
+
+zp_status series_fwd_run(const Plan &pl, int64_t M, const double *d_r, const double *d_theta, int64_t P,
+                         const double *d_c, int64_t B, int32_t prec, double *d_f, void *d_cache, void *d_ws,
+                         size_t ws_bytes, bool allow_pipe, hipStream_t s)
+{
+    const Plan *plan = &pl;
+    zp_status st = ZP_OK;
     const int ct = ct_of(prec);
     const bool have_cache = d_cache != nullptr;
     int64_t Pc = chunk_for(M, P, B, ct, true, false, have_cache, ws_bytes);
     if (Pc <= 0) return set_error(ZP_ERR_WORKSPACE, "workspace smaller than the minimum (zp_series_workspace)");
-    hipStream_t s = (hipStream_t)stream;
-    std::shared_ptr<Plan> plan;
-    st = get_plan(h_n, h_m, M, &plan);
-    if (st != ZP_OK) return st;
 
     // Pipelined chunks when the points are many and the workspace holds two
     // chunk buffers for the basis (bf16, or no cache); otherwise one stream.
     const bool ws_z = ct == CT_BF3 || !have_cache; // the basis goes through the workspace
     bool pipe = false;
     size_t zbuf = 0; // bytes of one chunk's basis buffer
-    const int64_t Pq = Pc == P ? pipe_chunk(P, B, ct) : 0;
+    const int64_t Pq = Pc == P && allow_pipe ? pipe_chunk(P, B, ct) : 0;
     if (Pq > 0) {
         const WsLayout Lq(M, Pq, B, ct, true, false, have_cache);
         zbuf = al(ct_bytes(ct) * (size_t)pad_up(M) * (size_t)Pq);
@@ -449,6 +461,27 @@ zp_status zp_series_fwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
         if (st != ZP_OK) return st;
     }
     return pipeline.finish();
+}
+
+} // namespace zp
+
+extern "C" {
+
+zp_status zp_series_fwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r, const double *d_theta,
+                        int64_t P, const double *d_c, int64_t B, int32_t prec, double *d_f, void *d_cache, void *d_ws,
+                        size_t ws_bytes, void *stream)
+{
+    zp_status st = series_fwd_checks(h_n, h_m, M, d_r, d_theta, P, d_c, B, prec, d_f);
+    if (st != ZP_OK || M == 0 || P == 0 || B == 0) return st;
+    if (!d_ws || ((uintptr_t)d_ws & 255)) return set_error(ZP_ERR_ARG, "workspace must be non-null and 256-byte aligned");
+    if ((uintptr_t)d_cache & 255) return set_error(ZP_ERR_ARG, "cache must be 256-byte aligned");
+    if (chunk_for(M, P, B, ct_of(prec), true, false, d_cache != nullptr, ws_bytes) <= 0)
+        return set_error(ZP_ERR_WORKSPACE, "workspace smaller than the minimum (zp_series_workspace)");
+    std::shared_ptr<Plan> plan;
+    st = get_plan(h_n, h_m, M, &plan);
+    if (st != ZP_OK) return st;
+    return series_fwd_run(*plan, M, d_r, d_theta, P, d_c, B, prec, d_f, d_cache, d_ws, ws_bytes, true,
+                          (hipStream_t)stream);
 }
 
 zp_status zp_series_bwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r, const double *d_theta,

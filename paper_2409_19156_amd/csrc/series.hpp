@@ -64,6 +64,19 @@ int coldot_bm(int ct);
 
 zp_status launch_gemm(const GemmDesc &g, hipStream_t s);
 
+// Series forward pieces shared by zp_series_fwd and its allocation-free
+// variant: argument checks (ZP_OK also for the M, P or B == 0 no-op), the
+// smallest workspace without a cache, and the work itself for a plan whose
+// device tables are in place.  allow_pipe lets the forward overlap chunks on
+// the library's helper stream (which it creates on first use).
+zp_status series_fwd_checks(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r,
+                            const double *d_theta, int64_t P, const double *d_c, int64_t B, int32_t prec,
+                            const double *d_f);
+size_t series_fwd_min_ws(int64_t M, int64_t P, int64_t B, int32_t prec);
+zp_status series_fwd_run(const Plan &plan, int64_t M, const double *d_r, const double *d_theta, int64_t P,
+                         const double *d_c, int64_t B, int32_t prec, double *d_f, void *d_cache, void *d_ws,
+                         size_t ws_bytes, bool allow_pipe, hipStream_t s);
+
 // dst (compute type, [R_pad][C_pad] or transposed [C_pad][R_pad]) from a
 // row-major FP64 src [R][C] (leading dimension lds); zero padding.
 zp_status launch_convert(const double *src, int64_t R, int64_t C, int64_t lds, int ct, void *dst, int64_t ldd,

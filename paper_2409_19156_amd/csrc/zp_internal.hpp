@@ -120,6 +120,16 @@ zp_status validate_modes(const int32_t *n, const int32_t *m, int64_t M, int64_t 
 // Host-side construction of a plan (no device work).
 std::shared_ptr<Plan> build_plan_host(const int32_t *n, const int32_t *m, int64_t M);
 
+// Byte offsets of a plan's device tables within one contiguous image (the
+// chains and pieces start at offset 0).
+struct PlanOffsets {
+    size_t coefs, emits, perm, total;
+};
+// Size of the image (and, if host is not null, the image itself).
+size_t plan_image(const Plan &p, std::vector<unsigned char> *host, PlanOffsets *o);
+// Point the plan's device table pointers into an image at base.
+void plan_bind(Plan &p, const void *base, const PlanOffsets &o);
+
 // Cached plan for the current device, uploaded on first use.
 zp_status get_plan(const int32_t *n, const int32_t *m, int64_t M, std::shared_ptr<Plan> *out);
 void clear_plans();

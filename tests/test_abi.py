@@ -65,6 +65,8 @@ def test_invalid_modes(lib, n, m):
                              FAKE, FAKE, FAKE, 1 << 20, None) == ERR_MODE
     assert lib.zp_series_jvp(n.ctypes.data, m.ctypes.data, n.size, FAKE, FAKE, 4, FAKE, 2, 0, FAKE, FAKE, FAKE,
                              FAKE, FAKE, 1 << 20, None) == ERR_MODE
+    assert lib.zp_series_fwd_noalloc(n.ctypes.data, m.ctypes.data, n.size, FAKE, FAKE, 4, FAKE, 2, 0, FAKE,
+                                     None) == ERR_MODE
 
 
 def test_order_mask_prec_and_sizes(lib):
@@ -89,6 +91,15 @@ def test_order_mask_prec_and_sizes(lib):
         assert lib.zp_series_fwd(nd, md, 2, FAKE, FAKE, 4, FAKE, 2, prec, FAKE, None, FAKE, 1 << 20, None) == ERR_PREC
     assert lib.zp_series_fwd(nd, md, 2, FAKE, FAKE, -4, FAKE, 2, 0, FAKE, None, FAKE, 1 << 20, None) == ERR_ARG
     assert lib.zp_series_fwd(nd, md, 2, FAKE, FAKE, 4, FAKE, -2, 0, FAKE, None, FAKE, 1 << 20, None) == ERR_ARG
+    # the allocation-free forward: precision, sizes and null pointers are checked first
+    for prec in (-1, 3):
+        assert lib.zp_series_fwd_noalloc(nd, md, 2, FAKE, FAKE, 4, FAKE, 2, prec, FAKE, None) == ERR_PREC
+    assert lib.zp_series_fwd_noalloc(nd, md, 2, FAKE, FAKE, -4, FAKE, 2, 0, FAKE, None) == ERR_ARG
+    assert lib.zp_series_fwd_noalloc(nd, md, 2, FAKE, FAKE, 4, FAKE, -2, 0, FAKE, None) == ERR_ARG
+    for i in (3, 4, 6, 9):
+        args = [nd, md, 2, FAKE, FAKE, 4, FAKE, 2, 0, FAKE, None]
+        args[i] = None
+        assert lib.zp_series_fwd_noalloc(*args) == ERR_ARG
     # workspace: null / misaligned / too small (all host-side)
     assert lib.zp_series_fwd(nd, md, 2, FAKE, FAKE, 4, FAKE, 2, 0, FAKE, None, None, 1 << 20, None) == ERR_ARG
     assert lib.zp_series_fwd(nd, md, 2, FAKE, FAKE, 4, FAKE, 2, 0, FAKE, None, ctypes.c_void_p(0x10008), 1 << 20,
@@ -115,6 +126,8 @@ def test_empty_problems_are_noops(lib):
     assert lib.zp_basis(n.ctypes.data, m.ctypes.data, 1, None, None, 0, 31, None, None) == OK
     assert lib.zp_series_fwd(n.ctypes.data, m.ctypes.data, 1, FAKE, FAKE, 4, FAKE, 0, 0, FAKE, None, FAKE, 0,
                              None) == OK
+    assert lib.zp_series_fwd_noalloc(n.ctypes.data, m.ctypes.data, 1, FAKE, FAKE, 4, FAKE, 0, 0, FAKE, None) == OK
+    assert lib.zp_series_fwd_noalloc(e.ctypes.data, e.ctypes.data, 0, FAKE, FAKE, 4, FAKE, 2, 0, FAKE, None) == OK
 
 
 def test_size_queries(lib):
