@@ -20,8 +20,13 @@
 //         cross products (hi.hi, hi.mid, mid.hi, hi.lo, mid.mid, lo.hi; the
 //         three dropped products are below 2^-24 relative)
 // The FP32-accumulating types add their FP32 accumulators into FP64 ones
-// every kFlush k and restart them, so FP32 rounding acts on partial sums of
-// at most kFlush terms.
+// every kFlush k (below) and restart them, so FP32 rounding acts on partial
+// sums of at most kFlush terms.  The bf16 MFMA's accumulation is biased
+// toward -infinity (measured on gfx950: about -1.2e-9 per unit-size product,
+// the same for positive and negative data, where the FP32 MFMA shows none),
+// which adds up over long sums; the bf16 x 3 contraction therefore negates B
+// on every other k step and subtracts that step's sums, so that the bias
+// alternates in sign and cancels.
 //
 // MFMA lane layouts (16x16 blocks): lane l supplies A[l%16][k] and B[k][l%16]
 // for k = l/16 (x4 shapes) or k = 8(l/16)..8(l/16)+7 (bf16 x32 shape).  It
@@ -42,7 +47,17 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 512; // eight waves per workgroup
-constexpr int kFlush = 128;
+// Flush interval (k terms) of the FP32 accumulators: every 16 k for FP32 (four
+// x4 products), every k step of 32 for bf16 x 3 (one bf16 product of depth 32
+// per cross term).  Sums that cancel after the contraction amplify its
+// rounding errors: the column-dot epilogue sums the product weighted by basis
+// derivatives over the modes, and the three-dimensional series folds partial
+// sums over the planes into Fourier modes.  Measured against the oracle on
+// the n <= 40 and n <= 64 series and the three-dimensional L = 32 workload,
+// flushing every 128 k left errors of up to 1.2e-6 (FP32) and 1.0e-6 (bf16 x
+// 3) relative to the largest output entry.
+template <int CT, int EPI>
+constexpr int kFlush = CT == CT_F32 ? (EPI == EPI_COLDOT ? 16 : 32) : 32;
 
 template <int CT> struct CTr;
 template <> struct CTr<CT_F64> {
@@ -235,6 +250,7 @@ __device__ __forceinline__ void gemm_body(const GemmDesc &g)
     constexpr int FM = WM / 16, FN = WN / 16;
     constexpr bool MIXED = CT != CT_F64;
     static_assert((BM / WM) * (BN / WN) * 64 == kThreads, "one wave tile per wave");
+    static_assert(CT != CT_BF3 || kFlush<CT, EPI> == BK, "bf16 steps alternate the sign of B: flush every step");
 
     __shared__ __attribute__((aligned(16))) T As[2][NP * TA::ELEMS];
     __shared__ __attribute__((aligned(16))) T Bs[2][NP * TB::ELEMS];
@@ -287,14 +303,16 @@ __device__ __forceinline__ void gemm_body(const GemmDesc &g)
                 for (int t = 0; t < 4; ++t) acc64[MIXED ? a : 0][MIXED ? b : 0][t] = 0.0;
         }
 
-    auto flush = [&]() {
+    // sign = -1 moves the FP32 sums of a step whose B fragments were negated.
+    auto flush = [&](double sign) {
         if (MIXED) {
 #pragma unroll
             for (int a = 0; a < FM; ++a)
 #pragma unroll
                 for (int b = 0; b < FN; ++b) {
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) acc64[MIXED ? a : 0][MIXED ? b : 0][t] += (double)acc[a][b][t];
+                    for (int t = 0; t < 4; ++t)
+                        acc64[MIXED ? a : 0][MIXED ? b : 0][t] += sign * (double)acc[a][b][t];
                     acc[a][b] = Acc{0, 0, 0, 0};
                 }
         }
@@ -349,6 +367,10 @@ __device__ __forceinline__ void gemm_body(const GemmDesc &g)
 #pragma unroll
                     for (int p = 0; p < 3; ++p)
                         fb[p] = *(const bf8 *)(LB + p * TB::ELEMS + TB::at(wn0 + b * 16 + lx, kk + 8 * lk));
+                    if constexpr (cur == 1) // odd steps: -B (see the flush)
+#pragma unroll
+                        for (int p = 0; p < 3; ++p)
+                            fb[p] = __builtin_bit_cast(bf8, __builtin_bit_cast(u4, fb[p]) ^ 0x80008000u);
 #pragma unroll
                     for (int a = 0; a < FM; ++a) {
                         // small cross products first, the leading one last
@@ -378,16 +400,21 @@ __device__ __forceinline__ void gemm_body(const GemmDesc &g)
                         else
                             acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a], fb[b], acc[a][b], 0, 0, 0);
                     }
+                if constexpr (MIXED && kFlush<CT, EPI> < BK)
+                    if ((kk + 4) % kFlush<CT, EPI> == 0) flush(1.0);
             }
         }
-        if (MIXED && ((t + 1) * BK) % kFlush == 0) flush();
+        if constexpr (CT == CT_BF3)
+            flush(cur == 1 ? -1.0 : 1.0); // every step (kFlush == BK)
+        else if (MIXED && kFlush<CT, EPI> >= BK && ((t + 1) * BK) % kFlush<CT, EPI> == 0)
+            flush(1.0);
         __syncthreads();
     };
     for (int t = 0; t < ntiles; t += 2) {
         step(t, std::integral_constant<int, 0>{});
         if (t + 1 < ntiles) step(t + 1, std::integral_constant<int, 1>{});
     }
-    flush();
+    flush(1.0);
 
     // Output row (within the 16-row block) of accumulator element t.
     auto row_of = [&](int t) -> int { return CT == CT_F64 ? lk + 4 * t : 4 * lk + t; };

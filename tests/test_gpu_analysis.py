@@ -5,7 +5,8 @@ same inputs, plus the round trip analysis(series(c)) = c on an exact grid.
 The quadrature points and weights given to both sides come from the oracle's
 rule (numpy's Gauss-Legendre) or from seeded random disc points.
 Error measure: ||GPU - oracle||_inf / ||oracle||_inf per coefficient tensor;
-1e-12 for FP64, 1e-6 for the FP32 and split-BF16x3 contractions.
+1e-12 for FP64, 5e-7 (half the 1e-6 bar of the mixed-precision series) for
+the FP32 and split-BF16x3 contractions.
 """
 from __future__ import annotations
 
@@ -19,7 +20,7 @@ import zp_workloads as W
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16x3": 1e-6}
+TOL = {"fp64": 1e-12, "fp32": 5e-7, "bf16x3": 5e-7}
 
 
 def _say(*a):
@@ -119,7 +120,7 @@ def test_round_trip_on_exact_grid(zp, oracle_mod, prec):
     back = zp.series_analysis(n, m, _dev(r), _dev(th), _dev(w), f, prec).cpu().numpy()
     e = _rel(back, c)
     _say(f"round trip L={L} prec={prec}: {e:.2e}")
-    assert e <= (1e-12 if prec == "fp64" else 1e-6)
+    assert e <= (1e-12 if prec == "fp64" else 5e-7)
 
 
 def test_analysis_with_library_grid(zp, oracle_mod):

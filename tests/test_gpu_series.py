@@ -3,8 +3,9 @@ against the oracle: the oracle basis (binary128, rounded to double) contracted
 in float64.
 
 Error measure per output tensor: ||GPU - oracle||_inf / ||oracle||_inf.
-Bounds: 1e-12 for the FP64 contraction; 1e-6 for the FP32 and split-BF16x3
-contractions (FP32 accumulation, flushed into FP64 every 128 terms).
+Bounds: 1e-12 for the FP64 contraction; 5e-7 for the FP32 and split-BF16x3
+contractions (FP32 accumulation, flushed into FP64 every 16 to 64 terms): half
+the 1e-6 relative error the mixed-precision series is held to.
 """
 from __future__ import annotations
 
@@ -18,7 +19,7 @@ import zp_workloads as W
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16x3": 1e-6}
+TOL = {"fp64": 1e-12, "fp32": 5e-7, "bf16x3": 5e-7}
 
 
 def _say(*a):

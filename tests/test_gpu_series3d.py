@@ -4,8 +4,8 @@ the oracle, which evaluates the full, duplicated mode list with no
 deduplication.
 
 Error measure per output tensor: ||GPU - oracle||_inf / ||oracle||_inf, with
-the planar series' bounds: 1e-12 for FP64, 1e-6 for the FP32 and split-BF16x3
-contractions.
+the planar series' bounds: 1e-12 for FP64, 5e-7 (half the 1e-6 bar of the
+mixed-precision series) for the FP32 and split-BF16x3 contractions.
 """
 from __future__ import annotations
 
@@ -19,7 +19,7 @@ import zp_workloads as W
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16x3": 1e-6}
+TOL = {"fp64": 1e-12, "fp32": 5e-7, "bf16x3": 5e-7}
 
 
 def _say(*a):

@@ -3,7 +3,8 @@ double backward / Hessian-vector products) against the oracle's term-by-term
 formula, and torch's double-backward checks through ZernikeSeries.
 
 Error measure: ||GPU - oracle||_inf / ||oracle||_inf per output tensor; 1e-12
-for FP64, 1e-6 for the FP32 and split-BF16x3 contractions.
+for FP64, 5e-7 (half the 1e-6 bar of the mixed-precision series) for the
+FP32 and split-BF16x3 contractions.
 """
 from __future__ import annotations
 
@@ -17,7 +18,7 @@ import zp_workloads as W
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16x3": 1e-6}
+TOL = {"fp64": 1e-12, "fp32": 5e-7, "bf16x3": 5e-7}
 NAMES = ("out_g", "out_c", "out_r", "out_t")
 
 
