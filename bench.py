@@ -32,9 +32,9 @@ FP64_PEAK_TFS = 78.6  # MI355X FP64 MFMA (dense), published
 # for 1048576 KiB written: x1.0).  Valid only for the kernel sources it was
 # taken on; reported as null once they change.
 TRAFFIC = {"sources": ("paper_2409_19156_amd/csrc/chain_kernel.hip", "paper_2409_19156_amd/csrc/zp_internal.hpp"),
-           "sha256": "7a122352f9b29a377d3163a901c0816075e17cd7d835df25dc2b8e5964001f5d",
+           "sha256": "065da48cd6ee87393c9dc0aac905c5fea11ba878e7e1b021cf18dce53efef03f",
            "fetch_kib": 468.5, "fetch_scale": 1048576.0 / 524299.5,
-           "write_kib": 424742.0, "write_scale": 1.0}
+           "write_kib": 424768.0, "write_scale": 1.0}
 
 
 def measured_traffic():
@@ -458,15 +458,20 @@ def main():
     value = entries / (ms * 1e-3)
     achieved = bytes_per_launch / (ms * 1e-3) / 1e9
 
-    # Reference streaming-write rate on the same buffer: torch's fill kernel.
-    for _ in range(3):
-        out.zero_()
-    ev0.record(stream)
-    for _ in range(20):
-        out.zero_()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    fill_gbs = out.numel() * 8 / (ev0.elapsed_time(ev1) / 20 * 1e-3) / 1e9
+    # Reference streaming-write rate on the same buffer: the library's trivial
+    # fill kernel (one 16-byte store per lane), non-temporal and plain; the
+    # faster of the two is the measured write peak.
+    fill_rates = {}
+    for nt in (1, 0):
+        for _ in range(3):
+            zp.stream_fill(out, 0.0, nontemporal=bool(nt))
+        ev0.record(stream)
+        for _ in range(20):
+            zp.stream_fill(out, 0.0, nontemporal=bool(nt))
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        fill_rates["nontemporal" if nt else "plain"] = out.numel() * 8 / (ev0.elapsed_time(ev1) / 20 * 1e-3) / 1e9
+    fill_gbs = max(fill_rates.values())
 
     res = {
         "metric": "Zernike basis entries/s FP64 (L=M=50) & series fwd+bwd speedup at stated err",
@@ -487,7 +492,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "chain_kernel<3, true, false, 2, false, false>", "bytes_per_launch": bytes_per_launch,
-                     "avg_launch_us": ms * 1e3, "measured_fill_GBs": fill_gbs,
+                     "avg_launch_us": ms * 1e3, "measured_fill_GBs": fill_gbs, "fill_GBs": fill_rates,
                      "frac_of_measured_fill": achieved / fill_gbs},
         "first_call_ms": first_call_ms,
         "timed_wall_ms": wall_ms,

@@ -343,6 +343,17 @@ zp_status zp_series_fwd_noalloc(const int32_t *h_n, const int32_t *h_m, int64_t 
                                 const double *d_theta, int64_t P, const double *d_c, int64_t B, int32_t prec,
                                 double *d_f, void *stream);
 
+/*
+ * zp_stream_fill -- d_out[i] = value for i < n: the device's streaming-write
+ * rate, measured by a trivial kernel (one 16-byte store per lane), the
+ * reference the basis kernel's store rate is compared with besides the
+ * published HBM peak (the roofline measurement of the basis, Sec. 4 timings).
+ *   d_out  device double[n], 16-byte aligned
+ *   nontemporal  nonzero: non-temporal stores; zero: plain stores
+ * Errors: ZP_ERR_ARG (n < 0, null or misaligned d_out), ZP_ERR_HIP.
+ */
+zp_status zp_stream_fill(double *d_out, int64_t n, double value, int32_t nontemporal, void *stream);
+
 /* Static description of a status code. */
 const char *zp_status_string(zp_status s);
 /* Detail of the last error raised on the calling host thread ("" if none). */

@@ -34,7 +34,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "libzpo.so")
+# ZP_ORACLE_LIB names a prebuilt copy to load instead (the sanitizer test
+# builds one with AddressSanitizer); build() then compiles nothing.
+_SO = os.environ.get("ZP_ORACLE_LIB") or os.path.join(_HERE, "libzpo.so")
 _lib = None
 
 MASK_Z, MASK_DR, MASK_DR2, MASK_DR3, MASK_DTHETA = 1, 2, 4, 8, 16
@@ -45,6 +47,8 @@ def build(force: bool = True) -> str:
     import subprocess
 
     src = os.path.join(_HERE, "zpo.c")
+    if os.environ.get("ZP_ORACLE_LIB"):
+        return _SO
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
         tmp = _SO + ".tmp"
         subprocess.run(

@@ -17,7 +17,7 @@ from ._lib import ZpError
 Z, DR, DR2, DR3, DTHETA = 1, 2, 4, 8, 16
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
-__all__ = ["radial", "radial_direct", "radial_zernike_recursion", "basis", "ZpError", "Z", "DR", "DR2", "DR3", "DTHETA", "PREC", "modes_i32"]
+__all__ = ["radial", "radial_direct", "radial_zernike_recursion", "basis", "stream_fill", "ZpError", "Z", "DR", "DR2", "DR3", "DTHETA", "PREC", "modes_i32"]
 
 
 def modes_i32(n, m):
@@ -43,6 +43,18 @@ def _points(x: torch.Tensor, name: str) -> torch.Tensor:
 
 def _stream(dev: torch.device) -> int:
     return torch.cuda.current_stream(dev).cuda_stream
+
+
+def stream_fill(out: torch.Tensor, value: float = 0.0, nontemporal: bool = True) -> torch.Tensor:
+    """out[:] = value by the library's streaming-write kernel (the benchmark's
+    write-rate reference).  ``out``: contiguous float64 GPU tensor."""
+    lib = _lib.load()
+    if not isinstance(out, torch.Tensor) or not out.is_cuda or out.dtype != torch.float64 or not out.is_contiguous():
+        raise TypeError("out must be a contiguous float64 GPU tensor")
+    with torch.cuda.device(out.device):
+        st = lib.zp_stream_fill(out.data_ptr(), out.numel(), float(value), 1 if nontemporal else 0, _stream(out.device))
+    _lib.check(st, "zp_stream_fill")
+    return out
 
 
 def radial(n, m, r: torch.Tensor, max_dr: int = 0, out: torch.Tensor | None = None) -> torch.Tensor:

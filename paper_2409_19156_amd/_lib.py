@@ -10,7 +10,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libzp.so")
+# ZP_LIBZP names another build of the same library to load (the sanitizer
+# test's AddressSanitizer build of the host code).
+LIB_PATH = os.environ.get("ZP_LIBZP") or os.path.join(_HERE, "libzp.so")
 
 ZP_OK = 0
 STATUS_NAMES = {0: "ZP_OK", 1: "ZP_ERR_MODE", 2: "ZP_ERR_ARG", 3: "ZP_ERR_ORDER", 4: "ZP_ERR_WORKSPACE",
@@ -20,7 +22,7 @@ STATUS_NAMES = {0: "ZP_OK", 1: "ZP_ERR_MODE", 2: "ZP_ERR_ARG", 3: "ZP_ERR_ORDER"
 EXPORTS = ("zp_radial", "zp_radial_direct", "zp_radial_zernike_recursion", "zp_basis", "zp_series_workspace", "zp_series_cache_bytes", "zp_series_fwd",
            "zp_series_bwd", "zp_series_jvp", "zp_series_bwd2_workspace", "zp_series_bwd2", "zp_series3d_workspace",
            "zp_series3d_cache_bytes", "zp_series3d_fwd", "zp_series3d_bwd", "zp_analysis_grid",
-           "zp_series_analysis_workspace", "zp_series_analysis", "zp_series_fwd_noalloc", "zp_status_string", "zp_last_error", "zp_cache_clear",
+           "zp_series_analysis_workspace", "zp_series_analysis", "zp_series_fwd_noalloc", "zp_stream_fill", "zp_status_string", "zp_last_error", "zp_cache_clear",
            "zp_abi_version")
 
 
@@ -62,6 +64,7 @@ def load() -> ctypes.CDLL:
         "zp_series_analysis_workspace": [i64, i64, i64, i32, szp, szp],
         "zp_series_analysis": [vp, vp, i64, vp, vp, vp, i64, vp, i64, i32, vp, vp, sz, vp],
         "zp_series_fwd_noalloc": [vp, vp, i64, vp, vp, i64, vp, i64, i32, vp, vp],
+        "zp_stream_fill": [vp, i64, ctypes.c_double, i32, vp],
     }
     for name, args in sig.items():
         if not hasattr(lib, name):

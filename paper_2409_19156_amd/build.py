@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libzp.so")
 SOURCES = ["zp_api.cpp", "plan.cpp", "series.cpp", "series3d.cpp", "chain_kernel.hip", "gemm.hip", "direct_kernel.hip",
-           "fourier_kernel.hip", "analysis.cpp", "analysis_kernel.hip", "zrec_kernel.hip", "noalloc.hip"]
+           "fourier_kernel.hip", "analysis.cpp", "analysis_kernel.hip", "zrec_kernel.hip", "noalloc.hip", "fill_kernel.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

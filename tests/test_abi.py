@@ -118,6 +118,13 @@ def test_order_mask_prec_and_sizes(lib):
                              None) == ERR_WS
 
 
+def test_stream_fill_arguments(lib):
+    assert lib.zp_stream_fill(FAKE, -1, 0.0, 1, None) == ERR_ARG
+    assert lib.zp_stream_fill(None, 8, 0.0, 1, None) == ERR_ARG
+    assert lib.zp_stream_fill(ctypes.c_void_p(0x10008), 8, 0.0, 0, None) == ERR_ARG
+    assert lib.zp_stream_fill(None, 0, 0.0, 1, None) == OK
+
+
 def test_empty_problems_are_noops(lib):
     n, m = _modes([2], [0])
     e = np.zeros(0, dtype=np.int32)
