@@ -237,7 +237,7 @@ template <> struct Cfg<CT_BF3> {
     static constexpr int BM = 128, BN = 128, BK = 32, WM = 64, WN = 32;
 };
 
-template <int CT, int ALAY, int BLAY, int EPI>
+template <int CT, int ALAY, int BLAY, int EPI, int NSET>
 __device__ __forceinline__ void gemm_body(const GemmDesc &g)
 {
     using C = Cfg<CT>;
@@ -325,8 +325,11 @@ __device__ __forceinline__ void gemm_body(const GemmDesc &g)
     // registers into the free LDS buffer, tile t+2 is fetched, and tile t is
     // multiplied out of the other buffer, so the LDS writes and the global
     // loads both overlap the MFMAs; one barrier per step.
-    typename TA::Regs ra[2];
-    typename TB::Regs rb[2];
+    // NSET = 1 keeps one set (the store of tile t+1 precedes the load of tile
+    // t+2 into the same registers): 8 to 16 fewer registers, for the builds
+    // capped at 128.
+    typename TA::Regs ra[NSET];
+    typename TB::Regs rb[NSET];
     if (ntiles > 0) {
         TA::load(ra[0], a_base, a_ld, a_sub, i0, kbeg);
         TB::load(rb[0], b_base, b_ld, b_sub, j0, kbeg);
@@ -334,8 +337,8 @@ __device__ __forceinline__ void gemm_body(const GemmDesc &g)
         TB::store(rb[0], Bs[0]);
     }
     if (ntiles > 1) {
-        TA::load(ra[1], a_base, a_ld, a_sub, i0, kbeg + BK);
-        TB::load(rb[1], b_base, b_ld, b_sub, j0, kbeg + BK);
+        TA::load(ra[NSET - 1], a_base, a_ld, a_sub, i0, kbeg + BK);
+        TB::load(rb[NSET - 1], b_base, b_ld, b_sub, j0, kbeg + BK);
     }
     __syncthreads();
 
@@ -343,12 +346,12 @@ __device__ __forceinline__ void gemm_body(const GemmDesc &g)
     auto step = [&](int t, auto cur_c) {
         constexpr int cur = decltype(cur_c)::value;
         if (t + 1 < ntiles) {
-            TA::store(ra[cur ^ 1], As[cur ^ 1]);
-            TB::store(rb[cur ^ 1], Bs[cur ^ 1]);
+            TA::store(ra[(cur ^ 1) % NSET], As[cur ^ 1]);
+            TB::store(rb[(cur ^ 1) % NSET], Bs[cur ^ 1]);
         }
         if (t + 2 < ntiles) {
-            TA::load(ra[cur], a_base, a_ld, a_sub, i0, kbeg + (int64_t)(t + 2) * BK);
-            TB::load(rb[cur], b_base, b_ld, b_sub, j0, kbeg + (int64_t)(t + 2) * BK);
+            TA::load(ra[cur % NSET], a_base, a_ld, a_sub, i0, kbeg + (int64_t)(t + 2) * BK);
+            TB::load(rb[cur % NSET], b_base, b_ld, b_sub, j0, kbeg + (int64_t)(t + 2) * BK);
         }
         const T *LA = As[cur];
         const T *LB = Bs[cur];
@@ -495,19 +498,20 @@ __device__ __forceinline__ void gemm_body(const GemmDesc &g)
 template <int CT, int ALAY, int BLAY, int EPI>
 __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc g)
 {
-    gemm_body<CT, ALAY, BLAY, EPI>(g);
+    gemm_body<CT, ALAY, BLAY, EPI, 2>(g);
 }
 
-// The same kernel compiled for four waves per SIMD (at most 128 registers), so
-// that two 512-thread workgroups share a CU and one's epilogue overlaps the
-// other's products.  Used for the FP64 forward (no spills; measured 6% faster)
-// and the FP64 column-dot (30 spilled registers, 4% faster: its epilogue reads
-// two 128 x 128 derivative tiles); the FP64 split-K (24 spilled registers, 11%
-// slower) and the FP32 and bf16 instances keep one workgroup per CU.
+// The same kernel compiled for four waves per SIMD (at most 128 registers,
+// one prefetch register set), so that two 512-thread workgroups share a CU
+// and one's epilogue and LDS phases overlap the other's products.  Used for
+// every FP64 contraction, where it fits without spills (the column-dot keeps
+// one 8-byte value in scratch across its main loop): forward 6%, split-K 4%
+// and column-dot 18% faster than one workgroup per CU.  The FP32 and bf16
+// instances need 170-220 registers and keep one workgroup per CU.
 template <int CT, int ALAY, int BLAY, int EPI>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void gemm_kernel_w4(GemmDesc g)
 {
-    gemm_body<CT, ALAY, BLAY, EPI>(g);
+    gemm_body<CT, ALAY, BLAY, EPI, 1>(g);
 }
 
 template <int CT, int ALAY, int BLAY, int EPI>
@@ -516,7 +520,7 @@ hipError_t launch_t(const GemmDesc &g, hipStream_t s)
     using C = Cfg<CT>;
     const dim3 grid((unsigned)((g.M + C::BM - 1) / C::BM), (unsigned)((g.N + C::BN - 1) / C::BN),
                     (unsigned)g.splits);
-    if constexpr (CT == CT_F64 && (EPI == EPI_STORE || EPI == EPI_COLDOT))
+    if constexpr (CT == CT_F64)
         hipLaunchKernelGGL((gemm_kernel_w4<CT, ALAY, BLAY, EPI>), grid, dim3(kThreads), 0, s, g);
     else
         hipLaunchKernelGGL((gemm_kernel<CT, ALAY, BLAY, EPI>), grid, dim3(kThreads), 0, s, g);
