@@ -458,6 +458,19 @@ def main():
     value = entries / (ms * 1e-3)
     achieved = bytes_per_launch / (ms * 1e-3) / 1e9
 
+    # The same basis through the polar-grid entry point (64 radii x 128 angles):
+    # bitwise the same output, one radial recurrence per lane instead of two.
+    rr, tt = W.cgl_polar_axes(64, 128)
+    rrd, ttd = torch.from_numpy(rr).to(dev), torch.from_numpy(tt).to(dev)
+    for _ in range(args.warmup):
+        zp.basis_polar(wl.n, wl.m, rrd, ttd, 31, out=out)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        zp.basis_polar(wl.n, wl.m, rrd, ttd, 31, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_polar = ev0.elapsed_time(ev1) / args.steps
+
     # Reference streaming-write rate on the same buffer: the library's trivial
     # fill kernel (one 16-byte store per lane), non-temporal and plain; the
     # faster of the two is the measured write peak.
@@ -494,6 +507,9 @@ def main():
                      "kernel": "chain_kernel<3, true, false, 2, false, false>", "bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": ms * 1e3, "measured_fill_GBs": fill_gbs, "fill_GBs": fill_rates,
                      "frac_of_measured_fill": achieved / fill_gbs},
+        "basis_polar": {"entry": "zp_basis_polar (64 radii x 128 angles, same output)", "ms": ms_polar,
+                        "entries_per_s": entries / (ms_polar * 1e-3),
+                        "frac_of_hbm_peak": bytes_per_launch / (ms_polar * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "first_call_ms": first_call_ms,
         "timed_wall_ms": wall_ms,
     }

@@ -112,6 +112,23 @@ zp_status zp_basis(const int32_t *h_n, const int32_t *h_m, int64_t M, const doub
                    const double *d_theta, int64_t P, uint32_t mask, double *d_out, void *stream);
 
 /*
+ * zp_basis_polar -- zp_basis on a tensor-product polar grid (the grids of the
+ * paper's timings and of spectral methods, Sec. 4): NR radii times NT
+ * angles, point p = i * NT + j at (r[i], theta[j]), angle fastest.  The
+ * output is exactly that of zp_basis given the NR * NT points (r_p, theta_p)
+ * (bit for bit): the radial recurrence runs once per radius and lane instead
+ * of once per point where NT is even.
+ *   d_r       device double[NR]
+ *   d_theta   device double[NT]
+ *   mask      as zp_basis
+ *   d_out     device double[popcount(mask) * M * NR * NT], layout as zp_basis
+ * Errors: as zp_basis; ZP_ERR_ARG also for NR or NT negative or NR * NT
+ * overflowing int64.
+ */
+zp_status zp_basis_polar(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r, int64_t NR,
+                         const double *d_theta, int64_t NT, uint32_t mask, double *d_out, void *stream);
+
+/*
  * zp_radial_direct -- the same outputs as zp_radial, evaluated directly from
  * the closed form Eq. (radial-part-eq): each term c_s r^(n-2s) (and its
  * r-derivatives) formed in FP64 and summed in order of s.  This is the

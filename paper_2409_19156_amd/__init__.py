@@ -17,7 +17,7 @@ from ._lib import ZpError
 Z, DR, DR2, DR3, DTHETA = 1, 2, 4, 8, 16
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
-__all__ = ["radial", "radial_direct", "radial_zernike_recursion", "basis", "stream_fill", "ZpError", "Z", "DR", "DR2", "DR3", "DTHETA", "PREC", "modes_i32"]
+__all__ = ["radial", "radial_direct", "radial_zernike_recursion", "basis", "basis_polar", "stream_fill", "ZpError", "Z", "DR", "DR2", "DR3", "DTHETA", "PREC", "modes_i32"]
 
 
 def modes_i32(n, m):
@@ -43,6 +43,31 @@ def _points(x: torch.Tensor, name: str) -> torch.Tensor:
 
 def _stream(dev: torch.device) -> int:
     return torch.cuda.current_stream(dev).cuda_stream
+
+
+def basis_polar(n, m, r: torch.Tensor, theta: torch.Tensor, mask: int = Z,
+                out: torch.Tensor | None = None) -> torch.Tensor:
+    """``basis`` on the tensor grid of NR radii ``r`` times NT angles
+    ``theta`` (point p = i * NT + j, angle fastest): float64
+    [popcount(mask), M, NR * NT], equal to ``basis`` on the flattened points."""
+    lib = _lib.load()
+    nh, mh = modes_i32(n, m)
+    r = _points(r, "r")
+    theta = _points(theta, "theta")
+    if theta.device != r.device:
+        raise ValueError("r and theta must be on one device")
+    M, NR, NT = nh.size, r.numel(), theta.numel()
+    nout = bin(int(mask) & 31).count("1")
+    shape = (max(nout, 1), M, NR * NT)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=r.device)
+    elif out.shape != shape or out.dtype != torch.float64 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 tensor [popcount(mask), M, NR * NT]")
+    with torch.cuda.device(r.device):
+        st = lib.zp_basis_polar(nh.ctypes.data, mh.ctypes.data, M, r.data_ptr(), NR, theta.data_ptr(), NT,
+                                int(mask), out.data_ptr(), _stream(r.device))
+    _lib.check(st, "zp_basis_polar")
+    return out
 
 
 def stream_fill(out: torch.Tensor, value: float = 0.0, nontemporal: bool = True) -> torch.Tensor:

@@ -19,7 +19,7 @@ STATUS_NAMES = {0: "ZP_OK", 1: "ZP_ERR_MODE", 2: "ZP_ERR_ARG", 3: "ZP_ERR_ORDER"
                 5: "ZP_ERR_HIP", 6: "ZP_ERR_PREC"}
 
 # Every symbol include/zp.h declares.
-EXPORTS = ("zp_radial", "zp_radial_direct", "zp_radial_zernike_recursion", "zp_basis", "zp_series_workspace", "zp_series_cache_bytes", "zp_series_fwd",
+EXPORTS = ("zp_radial", "zp_radial_direct", "zp_radial_zernike_recursion", "zp_basis", "zp_basis_polar", "zp_series_workspace", "zp_series_cache_bytes", "zp_series_fwd",
            "zp_series_bwd", "zp_series_jvp", "zp_series_bwd2_workspace", "zp_series_bwd2", "zp_series3d_workspace",
            "zp_series3d_cache_bytes", "zp_series3d_fwd", "zp_series3d_bwd", "zp_analysis_grid",
            "zp_series_analysis_workspace", "zp_series_analysis", "zp_series_fwd_noalloc", "zp_stream_fill", "zp_status_string", "zp_last_error", "zp_cache_clear",
@@ -49,6 +49,7 @@ def load() -> ctypes.CDLL:
         "zp_radial_direct": [vp, vp, i64, vp, i64, i32, vp, vp],
         "zp_radial_zernike_recursion": [vp, vp, i64, vp, i64, i32, vp, vp],
         "zp_basis": [vp, vp, i64, vp, vp, i64, u32, vp, vp],
+        "zp_basis_polar": [vp, vp, i64, vp, i64, vp, i64, u32, vp, vp],
         "zp_series_workspace": [i64, i64, i64, i32, szp, szp],
         "zp_series_cache_bytes": [i64, i64, i32, szp],
         "zp_series_fwd": [vp, vp, i64, vp, vp, i64, vp, i64, i32, vp, vp, vp, sz, vp],

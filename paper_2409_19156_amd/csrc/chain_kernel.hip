@@ -138,33 +138,44 @@ __device__ __forceinline__ double ipow(double x, int e)
 typedef double d2 __attribute__((ext_vector_type(2)));
 
 // NPL points per lane (1, or 2 for FP64-only outputs: each store then writes
-// 16 bytes per lane, 1 KB per wave).
-template <int J, bool ANG, bool KB, int NPL, bool DIR, bool SEC>
+// 16 bytes per lane, 1 KB per wave).  POLAR: the points are a tensor grid,
+// point p = i * nt + j at radius r[i] and angle theta[j]; with two points per
+// lane (nt even) both lie on one radius, and the lane's radial recurrence
+// (the state sized RS below) runs once for both.  Every value is formed
+// exactly as for the same point given as (r_p, theta_p).
+template <int J, bool ANG, bool KB, int NPL, bool DIR, bool SEC, bool POLAR>
 __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__ chains,
                                                        const Coef *__restrict__ coefs,
                                                        const Emit *__restrict__ emits,
                                                        const double *__restrict__ r,
                                                        const double *__restrict__ theta, int64_t P,
-                                                       Planes out)
+                                                       Planes out, int64_t nt)
 {
     static_assert(NPL == 1 || (NPL == 2 && !KB), "two points per lane only for plain FP64 planes");
     static_assert(!DIR || (ANG && J >= 1), "the directional derivative needs the basis and dZ/dr");
     static_assert(!SEC || (DIR && J >= 2 && NPL == 1 && !KB), "second-order planes need d2Z/dr2, one point per lane");
+    static_assert(!POLAR || (ANG && !KB && !DIR), "polar grids: plain basis planes");
+    constexpr int RS = POLAR ? 1 : NPL; // radial states per lane
     __shared__ Coef tab[kTabChunk];
 
     const Chain ch = chains[blockIdx.y];
     const int alpha = ch.alpha;
     const int64_t p0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * NPL;
+    // polar: radius row and first angle of the lane's points (nt even, p0 even)
+    const int64_t prow = POLAR ? p0 / nt : 0, pcol = POLAR ? p0 - prow * nt : 0;
 
-    bool live[NPL], high[NPL];
-    double x[NPL], s[NPL], s1[NPL], s2[NPL], cs[NPL], sn[NPL], tr[NPL], tt[NPL];
-    double w[NPL][J + 1], v[NPL][J + 1], d[NPL][J + 1];
+    bool live[NPL], high[RS];
+    double x[RS], s[RS], s1[RS], s2[RS], cs[NPL], sn[NPL], tr[NPL], tt[NPL];
+    double w[RS][J + 1], v[RS][J + 1], d[RS][J + 1];
 #pragma unroll
     for (int u = 0; u < NPL; ++u) {
         live[u] = p0 + u < P;
-        x[u] = live[u] ? r[p0 + u] : 0.0;
         tr[u] = (DIR && live[u] && out.dir_r) ? out.dir_r[p0 + u] : 0.0;  // tangent of r
         tt[u] = (DIR && live[u] && out.dir_th) ? out.dir_th[p0 + u] : 0.0; // tangent of theta
+    }
+#pragma unroll
+    for (int u = 0; u < RS; ++u) {
+        x[u] = !live[u] ? 0.0 : POLAR ? r[prow] : r[p0 + u];
         // Anchor and s(r), ds/dr, d2s/dr2.
         const double x2 = x[u] * x[u];
         high[u] = !(x2 < 0.5);
@@ -184,10 +195,18 @@ __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__
             for (int t = 0; t < i; ++t) f *= (double)(alpha - t);
             w[u][i] = f * ipow(x[u], alpha - i);
         }
+#pragma unroll
+        for (int i = 0; i <= J; ++i) {
+            v[u][i] = i == 0 ? 1.0 : 0.0;
+            d[u][i] = 0.0;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < NPL; ++u) {
         cs[u] = 0.0;
         sn[u] = 0.0;
         if (ANG) {
-            const double th = live[u] ? theta[p0 + u] : 0.0;
+            const double th = live[u] ? (POLAR ? theta[pcol + u] : theta[p0 + u]) : 0.0;
             // alpha * theta split exactly into ph + pe; then one first-order
             // correction of sincos(ph) for the tail pe.
             const double fa = (double)alpha;
@@ -197,11 +216,6 @@ __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__
             sincos(ph, &s0, &c0);
             sn[u] = __builtin_fma(pe, c0, s0);
             cs[u] = __builtin_fma(-pe, s0, c0);
-        }
-#pragma unroll
-        for (int i = 0; i <= J; ++i) {
-            v[u][i] = i == 0 ? 1.0 : 0.0;
-            d[u][i] = 0.0;
         }
     }
 
@@ -223,8 +237,10 @@ __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__
             nextK = e < e_end ? emits[e].K : INT_MAX;
             const bool is_sin = em.flags & 1;
             double val[5][NPL], vdir[NPL], vsr[NPL], vst[NPL];
+            // d^j R / dr^j of each radial state
+            double Rs[RS][J + 1];
 #pragma unroll
-            for (int u = 0; u < NPL; ++u) {
+            for (int u = 0; u < RS; ++u) {
                 // g^(j) = d^j/dr^j v(s(r))
                 double g[J + 1];
                 g[0] = v[u][0];
@@ -233,13 +249,17 @@ __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__
                 if (J >= 3) g[3] = __builtin_fma(s1[u] * s1[u] * s1[u], v[u][3], 3.0 * s1[u] * s2[u] * v[u][2]);
                 const double A = high[u] ? 1.0 : em.a_lo;
                 const double *wu = w[u];
-                double R[J + 1];
+                double *R = Rs[u];
                 R[0] = A * (wu[0] * g[0]);
                 if (J >= 1) R[1] = A * __builtin_fma(wu[0], g[1], wu[1] * g[0]);
                 if (J >= 2) R[2] = A * (__builtin_fma(wu[0], g[2], 2.0 * wu[1] * g[1]) + wu[2] * g[0]);
                 if (J >= 3)
                     R[3] = A * (__builtin_fma(wu[0], g[3], 3.0 * wu[1] * g[2]) +
                                 __builtin_fma(3.0 * wu[2], g[1], wu[3] * g[0]));
+            }
+#pragma unroll
+            for (int u = 0; u < NPL; ++u) {
+                const double *R = Rs[POLAR ? 0 : u];
                 const double fac = ANG ? (is_sin ? sn[u] : cs[u]) : 1.0;
 #pragma unroll
                 for (int q = 0; q <= J; ++q) val[q][u] = ANG ? R[q] * fac : R[q];
@@ -305,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__
         for (int kk = 0; kk < cnt; ++kk) {
             const Coef cf = tab[kk];
 #pragma unroll
-            for (int u = 0; u < NPL; ++u) {
+            for (int u = 0; u < RS; ++u) {
                 const double cc = high[u] ? cf.cc_hi : cf.cc_lo;
                 const double bs = high[u] ? cf.bs_hi : cf.bs_lo;
                 // All d use the step k-1 values of v; then v advances.
@@ -327,8 +347,9 @@ __global__ __launch_bounds__(kBlock) void chain_kernel(const Chain *__restrict__
 // resident slot on 256 CUs, so the heaviest chains do not form a tail.
 constexpr int64_t kMinWorkgroups = 8192;
 
-template <int J, bool ANG, bool KB, int NPL, bool DIR = false, bool SEC = false>
-hipError_t launch(const Plan &plan, const double *r, const double *th, int64_t P, const Planes &o, hipStream_t s)
+template <int J, bool ANG, bool KB, int NPL, bool DIR = false, bool SEC = false, bool POLAR = false>
+hipError_t launch(const Plan &plan, const double *r, const double *th, int64_t P, const Planes &o, hipStream_t s,
+                  int64_t nt = 0)
 {
     const int64_t tiles = (P + (int64_t)kBlock * NPL - 1) / ((int64_t)kBlock * NPL);
     // pieces when whole chains give too few workgroups, and while their count
@@ -337,8 +358,8 @@ hipError_t launch(const Plan &plan, const double *r, const double *th, int64_t P
     const Chain *list = use_pieces ? plan.d_pieces : plan.d_chains;
     const size_t count = use_pieces ? plan.pieces.size() : plan.chains.size();
     const dim3 grid((unsigned)tiles, (unsigned)count);
-    hipLaunchKernelGGL((chain_kernel<J, ANG, KB, NPL, DIR, SEC>), grid, dim3(kBlock), 0, s, list, plan.d_coefs, plan.d_emits,
-                       r, th, P, o);
+    hipLaunchKernelGGL((chain_kernel<J, ANG, KB, NPL, DIR, SEC, POLAR>), grid, dim3(kBlock), 0, s, list, plan.d_coefs,
+                       plan.d_emits, r, th, P, o, nt);
     return hipGetLastError();
 }
 
@@ -353,6 +374,40 @@ hipError_t launch_npl(const Plan &plan, const double *r, const double *th, int64
 }
 
 } // namespace
+
+zp_status launch_chain_kernel_polar(const Plan &plan, const double *d_r, int64_t nr, const double *d_theta, int64_t nt,
+                                    int J, const Planes &out, hipStream_t s)
+{
+    const int64_t P = nr * nt;
+    if (P <= 0 || plan.chains.empty()) return ZP_OK;
+    if ((P + kBlock - 1) / kBlock > (int64_t)INT_MAX) return set_error(ZP_ERR_ARG, "too many points for one launch");
+    bool all_f64 = true;
+    for (int q = 0; q < 5; ++q)
+        if (out.plane[q] && out.fmt[q] != F64) all_f64 = false;
+    if (out.kb || out.dir || out.kb_dir || out.sec_r || out.sec_t || J < 0 || J > 3)
+        return set_error(ZP_ERR_ARG, "internal: polar grids take plain basis planes");
+    const bool two = all_f64 && (nt % 2) == 0; // a lane's two points then share their radius
+    hipError_t e;
+    switch (J) {
+    case 0:
+        e = two ? launch<0, true, false, 2, false, false, true>(plan, d_r, d_theta, P, out, s, nt)
+                : launch<0, true, false, 1, false, false, true>(plan, d_r, d_theta, P, out, s, nt);
+        break;
+    case 1:
+        e = two ? launch<1, true, false, 2, false, false, true>(plan, d_r, d_theta, P, out, s, nt)
+                : launch<1, true, false, 1, false, false, true>(plan, d_r, d_theta, P, out, s, nt);
+        break;
+    case 2:
+        e = two ? launch<2, true, false, 2, false, false, true>(plan, d_r, d_theta, P, out, s, nt)
+                : launch<2, true, false, 1, false, false, true>(plan, d_r, d_theta, P, out, s, nt);
+        break;
+    default:
+        e = two ? launch<3, true, false, 2, false, false, true>(plan, d_r, d_theta, P, out, s, nt)
+                : launch<3, true, false, 1, false, false, true>(plan, d_r, d_theta, P, out, s, nt);
+        break;
+    }
+    return hip_check(e, "chain_kernel launch");
+}
 
 zp_status launch_chain_kernel(const Plan &plan, const double *d_r, const double *d_theta, int64_t P, int J,
                               bool angular, const Planes &out, hipStream_t s)

@@ -94,6 +94,33 @@ zp_status zp_basis(const int32_t *h_n, const int32_t *h_m, int64_t M, const doub
     return launch_chain_kernel(*plan, d_r, d_theta, P, J, true, o, (hipStream_t)stream);
 }
 
+zp_status zp_basis_polar(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r, int64_t NR,
+                         const double *d_theta, int64_t NT, uint32_t mask, double *d_out, void *stream)
+{
+    zp_status st = check_modes_arg(h_n, h_m, M);
+    if (st != ZP_OK) return st;
+    if (mask == 0 || (mask & ~31u)) return set_error(ZP_ERR_ARG, "mask must be a nonzero subset of bits 0..4");
+    if (NR < 0 || NT < 0) return set_error(ZP_ERR_ARG, "NR < 0 or NT < 0");
+    if (NR > 0 && NT > INT64_MAX / NR) return set_error(ZP_ERR_ARG, "NR * NT overflows");
+    const int64_t P = NR * NT;
+    if (M == 0 || P == 0) return ZP_OK;
+    if (!d_r || !d_theta || !d_out) return set_error(ZP_ERR_ARG, "null point or output pointer");
+    std::shared_ptr<Plan> plan;
+    st = get_plan(h_n, h_m, M, &plan);
+    if (st != ZP_OK) return st;
+    Planes o{};
+    o.ld = P;
+    int np = 0, J = 0;
+    for (int q = 0; q < 5; ++q) {
+        if (!((mask >> q) & 1u)) continue;
+        o.plane[q] = d_out + (size_t)np * (size_t)M * (size_t)P;
+        o.fmt[q] = F64;
+        ++np;
+        if (q >= 1 && q <= 3) J = q;
+    }
+    return launch_chain_kernel_polar(*plan, d_r, NR, d_theta, NT, J, o, (hipStream_t)stream);
+}
+
 zp_status zp_radial_direct(const int32_t *h_n, const int32_t *h_m, int64_t M, const double *d_r, int64_t P,
                            int32_t max_dr, double *d_out, void *stream)
 {

@@ -180,6 +180,11 @@ struct Planes {
 zp_status launch_chain_kernel(const Plan &plan, const double *d_r, const double *d_theta, int64_t P,
                               int J, bool angular, const Planes &out, hipStream_t s);
 
+// The basis on a tensor grid: point p = i * nt + j at radius r[i], angle
+// theta[j] (i < nr, j < nt), into plain planes with ld = nr * nt.
+zp_status launch_chain_kernel_polar(const Plan &plan, const double *d_r, int64_t nr, const double *d_theta, int64_t nt,
+                                    int J, const Planes &out, hipStream_t s);
+
 // Error plumbing.
 zp_status set_error(zp_status s, const std::string &msg);
 zp_status hip_check(hipError_t e, const char *what);

@@ -59,6 +59,7 @@ def test_invalid_modes(lib, n, m):
     assert lib.zp_radial_direct(n.ctypes.data, m.ctypes.data, n.size, FAKE, 4, 0, FAKE, None) == ERR_MODE
     assert lib.zp_radial_zernike_recursion(n.ctypes.data, m.ctypes.data, n.size, FAKE, 4, 0, FAKE, None) == ERR_MODE
     assert lib.zp_basis(n.ctypes.data, m.ctypes.data, n.size, FAKE, FAKE, 4, 1, FAKE, None) == ERR_MODE
+    assert lib.zp_basis_polar(n.ctypes.data, m.ctypes.data, n.size, FAKE, 2, FAKE, 2, 1, FAKE, None) == ERR_MODE
     assert lib.zp_series_fwd(n.ctypes.data, m.ctypes.data, n.size, FAKE, FAKE, 4, FAKE, 2, 0, FAKE, None, FAKE,
                              1 << 20, None) == ERR_MODE
     assert lib.zp_series_bwd(n.ctypes.data, m.ctypes.data, n.size, FAKE, FAKE, 4, FAKE, 2, 0, FAKE, None, FAKE,
@@ -87,6 +88,14 @@ def test_order_mask_prec_and_sizes(lib):
     assert lib.zp_radial(nd, md, 2, FAKE, 4, 0, None, None) == ERR_ARG
     assert lib.zp_radial(None, md, 2, FAKE, 4, 0, FAKE, None) == ERR_ARG
     assert lib.zp_basis(nd, md, 2, FAKE, None, 4, 1, FAKE, None) == ERR_ARG
+    # polar grids: sizes, mask and pointers are checked first
+    assert lib.zp_basis_polar(nd, md, 2, FAKE, -1, FAKE, 4, 1, FAKE, None) == ERR_ARG
+    assert lib.zp_basis_polar(nd, md, 2, FAKE, 3, FAKE, -4, 1, FAKE, None) == ERR_ARG
+    assert lib.zp_basis_polar(nd, md, 2, FAKE, 1 << 40, FAKE, 1 << 40, 1, FAKE, None) == ERR_ARG
+    assert lib.zp_basis_polar(nd, md, 2, FAKE, 3, FAKE, 4, 0, FAKE, None) == ERR_ARG
+    assert lib.zp_basis_polar(nd, md, 2, FAKE, 3, None, 4, 1, FAKE, None) == ERR_ARG
+    assert lib.zp_basis_polar(nd, md, 2, FAKE, 3, FAKE, 4, 1, None, None) == ERR_ARG
+    assert lib.zp_basis_polar(nd, md, 2, None, 0, None, 4, 31, None, None) == OK
     for prec in (-1, 3):
         assert lib.zp_series_fwd(nd, md, 2, FAKE, FAKE, 4, FAKE, 2, prec, FAKE, None, FAKE, 1 << 20, None) == ERR_PREC
     assert lib.zp_series_fwd(nd, md, 2, FAKE, FAKE, -4, FAKE, 2, 0, FAKE, None, FAKE, 1 << 20, None) == ERR_ARG

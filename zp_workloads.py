@@ -53,14 +53,21 @@ def ansi_modes(nmax: int):
     return np.array(n, dtype=np.int32), np.array(m, dtype=np.int32)
 
 
-def cgl_polar_grid(nr: int = 64, nt: int = 128):
-    """nr Chebyshev-Gauss-Lobatto radii mapped to [0, 1], ascending, with the
-    end points exactly 0 and 1, times nt equispaced theta in [0, 2 pi).
-    Point p = nt * i + j (theta fastest)."""
+def cgl_polar_axes(nr: int = 64, nt: int = 128):
+    """The two axes of the polar grid: nr Chebyshev-Gauss-Lobatto radii
+    mapped to [0, 1], ascending, with the end points exactly 0 and 1, and nt
+    equispaced theta in [0, 2 pi)."""
     i = np.arange(nr, dtype=np.float64)
     rr = np.sin(np.pi * i / (2.0 * (nr - 1))) ** 2  # (1 - cos(pi i/(nr-1))) / 2
     rr[0], rr[-1] = 0.0, 1.0
     th = 2.0 * np.pi * np.arange(nt, dtype=np.float64) / nt
+    return rr, th
+
+
+def cgl_polar_grid(nr: int = 64, nt: int = 128):
+    """The polar grid's points, flattened: point p = nt * i + j (theta
+    fastest) at (rr[i], th[j]) of ``cgl_polar_axes``."""
+    rr, th = cgl_polar_axes(nr, nt)
     r = np.repeat(rr, nt)
     theta = np.tile(th, nr)
     return r, theta
@@ -150,7 +157,7 @@ def n_entries(M: int, P: int, nout: int) -> int:
 
 
 __all__ = [
-    "radial_pairs", "ansi_modes", "cgl_polar_grid", "clustered_r", "disc_points", "Workload",
+    "radial_pairs", "ansi_modes", "cgl_polar_axes", "cgl_polar_grid", "clustered_r", "disc_points", "Workload",
     "radial_n16", "basis_L50", "radial_n200", "series_n40", "series_n64", "n_entries",
 ]
 
