@@ -581,6 +581,83 @@ __device__ __forceinline__ void put(void *dst, int ct, int64_t idx, int64_t sub,
     }
 }
 
+// put() for the two adjacent elements idx, idx + 1 (idx even, dst aligned):
+// one 16-, 8- or 2 x 3 x 2-byte store instead of two, the same values.
+__device__ __forceinline__ void put2(void *dst, int ct, int64_t idx, int64_t sub, double v0, double v1)
+{
+    if (ct == CT_F64) {
+        typedef double dd2 __attribute__((ext_vector_type(2)));
+        *(dd2 *)((double *)dst + idx) = dd2{v0, v1};
+    } else if (ct == CT_F32) {
+        typedef float ff2 __attribute__((ext_vector_type(2)));
+        *(ff2 *)((float *)dst + idx) = ff2{(float)v0, (float)v1};
+    } else {
+        uint16_t h[2], m[2], l[2];
+        const double v[2] = {v0, v1};
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            h[u] = bf16_rne((float)v[u]);
+            const double r1 = v[u] - bf16_val(h[u]);
+            m[u] = bf16_rne((float)r1);
+            const double r2 = r1 - bf16_val(m[u]);
+            l[u] = bf16_rne((float)r2);
+        }
+        uint32_t *b = (uint32_t *)((uint16_t *)dst + idx);
+        const int64_t sub2 = sub / 2; // planes sub elements apart (sub even)
+        b[0] = h[0] | ((uint32_t)h[1] << 16);
+        b[sub2] = m[0] | ((uint32_t)m[1] << 16);
+        b[2 * sub2] = l[0] | ((uint32_t)l[1] << 16);
+    }
+}
+
+// Row conversion: dst[r][c] for r < gridDim.x (the padded rows), c < ldd
+// (even), two columns per lane; zero outside src's R x C.
+__global__ __launch_bounds__(256) void convert_rows_kernel(const double *__restrict__ src, int64_t R, int64_t C,
+                                                           int64_t lds, int ct, void *dst, int64_t ldd, int64_t sub)
+{
+    const int64_t r = blockIdx.x;
+    const int64_t c = ((int64_t)blockIdx.y * 256 + threadIdx.x) * 2;
+    if (c >= ldd) return;
+    double v0 = 0.0, v1 = 0.0;
+    if (r < R) {
+        if (c < C) v0 = src[r * lds + c];
+        if (c + 1 < C) v1 = src[r * lds + c + 1];
+    }
+    put2(dst, ct, r * ldd + c, sub, v0, v1);
+}
+
+// Transposing conversion through a 64 x 64 LDS tile: dst_t[c][r] = src[r][c]
+// (dst_t [gridDim.y * 64][ldt]), and, if dst_n is not null, the plain copy
+// dst_n[r][c] ([gridDim.x * 64][ldn]) from the same reads.  Zero outside
+// src's R x C; two elements per lane on each store.
+__global__ __launch_bounds__(256) void convert_t64_kernel(const double *__restrict__ src, int64_t R, int64_t C,
+                                                          int64_t lds, int ct, void *dst_t, int64_t ldt,
+                                                          int64_t sub_t, void *dst_n, int64_t ldn, int64_t sub_n)
+{
+    __shared__ double tile[64][65];
+    const int64_t r0 = (int64_t)blockIdx.x * 64; // src rows = dst_t columns
+    const int64_t c0 = (int64_t)blockIdx.y * 64; // src cols = dst_t rows
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int idx = i * 256 + t;
+        const int y = idx >> 5, x = (idx & 31) * 2;
+        const int64_t r = r0 + y, c = c0 + x;
+        const double v0 = (r < R && c < C) ? src[r * lds + c] : 0.0;
+        const double v1 = (r < R && c + 1 < C) ? src[r * lds + c + 1] : 0.0;
+        tile[y][x] = v0;
+        tile[y][x + 1] = v1;
+        if (dst_n) put2(dst_n, ct, r * ldn + c, sub_n, v0, v1);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int idx = i * 256 + t;
+        const int cy = idx >> 5, rx = (idx & 31) * 2;
+        put2(dst_t, ct, (c0 + cy) * ldt + r0 + rx, sub_t, tile[rx][cy], tile[rx + 1][cy]);
+    }
+}
+
 // Direct conversion: dst[r][c] for r < rows_pad, c < ldd.
 __global__ void convert_kernel(const double *__restrict__ src, int64_t R, int64_t C, int64_t lds, int ct, void *dst,
                                int64_t ldd, int64_t rows_pad, int64_t sub)
@@ -722,13 +799,35 @@ zp_status launch_convert(const double *src, int64_t R, int64_t C, int64_t lds, i
                          int64_t rows_pad, int64_t sub, bool transpose, hipStream_t s)
 {
     if (!transpose) {
-        hipLaunchKernelGGL(convert_kernel, dim3(grid_for(rows_pad * ldd, 256)), dim3(256), 0, s, src, R, C, lds, ct,
-                           dst, ldd, rows_pad, sub);
+        if (ldd % 2 == 0 && sub % 2 == 0 && rows_pad <= 0x7FFFFFFF && ((uintptr_t)dst & 15) == 0) {
+            const dim3 grid((unsigned)rows_pad, (unsigned)((ldd / 2 + 255) / 256));
+            hipLaunchKernelGGL(convert_rows_kernel, grid, dim3(256), 0, s, src, R, C, lds, ct, dst, ldd, sub);
+        } else {
+            hipLaunchKernelGGL(convert_kernel, dim3(grid_for(rows_pad * ldd, 256)), dim3(256), 0, s, src, R, C, lds,
+                               ct, dst, ldd, rows_pad, sub);
+        }
+    } else if (ldd % 64 == 0 && rows_pad % 64 == 0 && sub % 2 == 0) {
+        // dst is [rows_pad (>= C, padded)][ldd (>= R, padded)]
+        const dim3 grid((unsigned)(ldd / 64), (unsigned)(rows_pad / 64));
+        hipLaunchKernelGGL(convert_t64_kernel, grid, dim3(256), 0, s, src, R, C, lds, ct, dst, ldd, sub, (void *)nullptr,
+                           (int64_t)0, (int64_t)0);
     } else {
-        // dst is [rows_pad (>= C, padded)][ldd (>= R, padded)]; both multiples of 32
+        // both multiples of 32
         const dim3 grid((unsigned)(ldd / 32), (unsigned)(rows_pad / 32));
         hipLaunchKernelGGL(convert_t_kernel, grid, dim3(256), 0, s, src, R, C, lds, ct, dst, ldd, sub);
     }
+    return hip_check(hipGetLastError(), "convert launch");
+}
+
+zp_status launch_convert_both(const double *src, int64_t R, int64_t C, int64_t lds, int ct, void *dst_n, int64_t ldn,
+                              int64_t sub_n, void *dst_t, int64_t ldt, int64_t sub_t, hipStream_t s)
+{
+    // dst_n [ldt][ldn] and dst_t [ldn][ldt]: ldt >= R and ldn >= C, both multiples of 64
+    if (ldt % 64 || ldn % 64 || sub_n % 2 || sub_t % 2 || ((uintptr_t)dst_n & 15) || ((uintptr_t)dst_t & 15))
+        return set_error(ZP_ERR_ARG, "internal: fused conversion needs 64-multiple, aligned operands");
+    const dim3 grid((unsigned)(ldt / 64), (unsigned)(ldn / 64));
+    hipLaunchKernelGGL(convert_t64_kernel, grid, dim3(256), 0, s, src, R, C, lds, ct, dst_t, ldt, sub_t, dst_n, ldn,
+                       sub_n);
     return hip_check(hipGetLastError(), "convert launch");
 }
 

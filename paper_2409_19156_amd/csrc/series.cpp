@@ -546,12 +546,12 @@ zp_status zp_series_bwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
         // has that layout and is read in place.
         const bool g_in_place = ct == CT_F64 && B == Bp && pc == pcp && ((uintptr_t)d_g & 15) == 0;
         const void *gbuf = g_in_place ? (const void *)(d_g + p0 * B) : (const void *)(ws + L.g_off);
-        if (!g_in_place) {
-            st = launch_convert(d_g + p0 * B, pc, B, B, ct, ws + L.g_off, Bp, pcp, pcp * Bp, false, s);
+        if (ct == CT_BF3 && d_grad_c) { // both layouts from one read of g
+            st = launch_convert_both(d_g + p0 * B, pc, B, B, ct, ws + L.g_off, Bp, pcp * Bp, ws + L.gt_off, pcp,
+                                     Bp * pcp, s);
             if (st != ZP_OK) return st;
-        }
-        if (ct == CT_BF3 && d_grad_c) {
-            st = launch_convert(d_g + p0 * B, pc, B, B, ct, ws + L.gt_off, pcp, Bp, Bp * pcp, true, s);
+        } else if (!g_in_place) {
+            st = launch_convert(d_g + p0 * B, pc, B, B, ct, ws + L.g_off, Bp, pcp, pcp * Bp, false, s);
             if (st != ZP_OK) return st;
         }
         if (d_grad_c) {
@@ -890,15 +890,15 @@ zp_status zp_series_bwd2(const int32_t *h_n, const int32_t *h_m, int64_t M, cons
         // read in place in FP64 when it already has that layout
         const bool g_in_place = ct == CT_F64 && B == Bp && pc == pcp && ((uintptr_t)d_g & 15) == 0;
         const void *gbuf = g_in_place ? (const void *)(d_g + p0 * B) : (const void *)(ws + L.g_off);
-        if (!g_in_place) {
+        if (run_c && ct == CT_BF3) { // both layouts from one read of g
+            st = launch_convert_both(d_g + p0 * B, pc, B, B, ct, ws + L.g_off, Bp, pcp * Bp, ws + L.gt_off, pcp,
+                                     Bp * pcp, s);
+            if (st != ZP_OK) return st;
+        } else if (!g_in_place) {
             st = launch_convert(d_g + p0 * B, pc, B, B, ct, ws + L.g_off, Bp, pcp, pcp * Bp, false, s);
             if (st != ZP_OK) return st;
         }
         if (run_c) {
-            if (ct == CT_BF3) {
-                st = launch_convert(d_g + p0 * B, pc, B, B, ct, ws + L.gt_off, pcp, Bp, Bp * pcp, true, s);
-                if (st != ZP_OK) return st;
-            }
             GemmDesc g{};
             g.ct = ct;
             g.a = Operand{ws + L.d_off, pcp, Mp * pcp, zlay_of(ct)}; // A(i=q, k=p) = D[q][p]

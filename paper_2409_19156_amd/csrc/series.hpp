@@ -82,6 +82,11 @@ zp_status series_fwd_run(const Plan &plan, int64_t M, const double *d_r, const d
 zp_status launch_convert(const double *src, int64_t R, int64_t C, int64_t lds, int ct, void *dst, int64_t ldd,
                          int64_t rows_pad, int64_t sub, bool transpose, hipStream_t s);
 
+// Both layouts from one pass over src [R][C]: dst_n [ldt][ldn] = src and
+// dst_t [ldn][ldt] = src^T, zero padded (ldt >= R, ldn >= C, multiples of 64).
+zp_status launch_convert_both(const double *src, int64_t R, int64_t C, int64_t lds, int ct, void *dst_n, int64_t ldn,
+                              int64_t sub_n, void *dst_t, int64_t ldt, int64_t sub_t, hipStream_t s);
+
 // dst[c][e] = src[perm[e]][c] (e < R, zero padded) for columns e < ncols of
 // dst [rows_pad][ldd] (ncols a multiple of 32, <= ldd).
 zp_status launch_convert_gather_t(const double *src, const int32_t *perm, int64_t R, int64_t C, int64_t lds,
