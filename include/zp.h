@@ -26,8 +26,9 @@
  *     each plane is the paper's (points x modes) output array in column-major
  *     order (Algorithms 1 and 2, "Output").
  *   - Every call is asynchronous on `stream` (a hipStream_t; NULL means the
- *     default stream).  The series forward and forward-mode derivative may
- *     run part of their work on one library-owned stream per device (default
+ *     default stream).  The series forward, backward and forward-mode
+ *     derivative may run part of their work on one library-owned stream per
+ *     device (default
  *     priority, created on first use); it waits for `stream` through an event
  *     at the start of the call, and `stream` waits for it before the call's
  *     last piece of work, so to the caller the call is ordered on `stream`
