@@ -152,7 +152,8 @@ def series_leg(steps: int, warmup: int):
     modes, 65536 disc points, 1024 coefficient sets): the forward alone, then
     forward + backward; each precision's error per output against the oracle
     on a fixed sample (f on 128 points x 64 sets, grad_r and grad_theta on the
-    128 points, grad_c for all modes on 8 sets)."""
+    128 points, grad_c for all modes on 8 sets).  Then one GPU's share of an
+    eight-way split by points (P/8 points), forward + backward."""
     import torch
 
     import paper_2409_19156_amd as zp
@@ -165,6 +166,7 @@ def series_leg(steps: int, warmup: int):
     out = {}
     stream = torch.cuda.current_stream(dev)
     oref = _oracle_sample("series_n64_oracle_sample.npz", wl)
+    ps = wl.P // 8
     for prec in ("fp64", "fp32", "bf16x3"):
         full, _, cb = zp.series_sizes(wl.M, wl.P, wl.B, prec)
         ws = torch.empty(full, dtype=torch.uint8, device=dev)
@@ -197,14 +199,42 @@ def series_leg(steps: int, warmup: int):
         entry["algorithmic_tflops"] = entry["gemm_gflop"] / ms
         if oref is not None:
             entry["err_vs_oracle"] = _sample_errors(oref, *(x.cpu().numpy() for x in res))
+        full_rows = [x[:ps].clone() for x in (res[0], res[2], res[3])]  # f, grad_r, grad_theta of the shard
+        del ws, cache, res[:]
+        torch.cuda.empty_cache()
+
+        # One GPU's share of an eight-way split by points: the first P/8 points,
+        # all modes and sets.  f, grad_r and grad_theta of those points must
+        # equal the full run's; grad_c is that GPU's partial sum before the
+        # all-reduce.
+        full, _, cb = zp.series_sizes(wl.M, ps, wl.B, prec)
+        ws = torch.empty(full, dtype=torch.uint8, device=dev)
+        cache = torch.empty(cb, dtype=torch.uint8, device=dev)
+        rs, ts, gs = r[:ps], th[:ps], g[:ps]
+
+        def step_shard():
+            f = zp.series_forward(wl.n, wl.m, rs, ts, c, prec, cache=cache, ws=ws)
+            res[:] = (f,) + zp.series_backward(wl.n, wl.m, rs, ts, c, gs, prec, cache=cache, ws=ws)
+
+        for _ in range(warmup):
+            step_shard()
+        torch.cuda.synchronize()
+        ms_s = timed(step_shard)
+        gflop_s = 3 * 2.0 * ps * wl.M * wl.B / 1e9
+        same = all(bool(torch.equal(a, b)) for a, b in zip(full_rows, (res[0], res[2], res[3])))
+        entry["shard_8way"] = {"points": ps, "ms_fwd_bwd": ms_s, "algorithmic_tflops": gflop_s / ms_s,
+                               "per_point_outputs_equal_full_run": same}
         out[prec] = entry
-        del ws, cache
+        del ws, cache, res[:], full_rows
         torch.cuda.empty_cache()
     out["speedup_bf16x3_vs_fp64"] = out["fp64"]["ms_fwd_bwd"] / out["bf16x3"]["ms_fwd_bwd"]
     out["speedup_fp32_vs_fp64"] = out["fp64"]["ms_fwd_bwd"] / out["fp32"]["ms_fwd_bwd"]
     out["workload"] = "series_n64: ANSI n<=64 (2145 modes), 65536 disc points, 1024 sets, fwd+bwd (c, r, theta)"
     out["err_sample"] = ("oracle (stored) on 128 fixed points x 64 sets (f), the same points (grad_r, grad_theta), "
                          "8 sets x all modes (grad_c)" if oref is not None else "oracle sample missing")
+    out["shard_8way"] = ("one GPU's share of an 8-way split by points (the first P/8 points, all modes and sets), "
+                         "forward + backward without the all-reduce of grad_c; its f, grad_r and grad_theta are "
+                         "compared with the full run's rows for those points")
     return out
 
 

@@ -518,13 +518,14 @@ zp_status zp_series_bwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
     }
     const CacheLayout CL(M, P, ct);
     const size_t zsz = zsize_of(ct);
-    // With one chunk and few output tiles (fewer than four per CU), the dL/dr,
-    // dL/dtheta contraction runs on the helper stream beside the dL/dc
+    // With one chunk and few output tiles (fewer than eight per CU), the
+    // dL/dr, dL/dtheta contraction runs on the helper stream beside the dL/dc
     // contraction, since neither fills the chip alone: the n <= 40 series
-    // (896 tiles) went 0.61 -> 0.56 ms; the n <= 64 one (8704 tiles) lost 5%
-    // with the overlap and keeps one stream.
+    // (896 tiles) went 0.61 -> 0.56 ms, n <= 64 on 8192 points (1088 tiles)
+    // 4-7% faster; n <= 64 on 65536 points (8704 tiles) lost 5% with the
+    // overlap and keeps one stream.
     const int64_t rt_tiles = ((M + 127) / 128) * ((Pc + 127) / 128);
-    ChunkPipe side(s, d_grad_c && need_rt && Pc >= P && rt_tiles < 4 * (int64_t)device_cus());
+    ChunkPipe side(s, d_grad_c && need_rt && Pc >= P && rt_tiles < 8 * (int64_t)device_cus());
     for (int64_t p0 = 0; p0 < P; p0 += Pc) {
         const int64_t pc = std::min(Pc, P - p0);
         const int64_t pcp = pad_up(pc);
