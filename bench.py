@@ -32,9 +32,9 @@ FP64_PEAK_TFS = 78.6  # MI355X FP64 MFMA (dense), published
 # for 1048576 KiB written: x1.0).  Valid only for the kernel sources it was
 # taken on; reported as null once they change.
 TRAFFIC = {"sources": ("paper_2409_19156_amd/csrc/chain_kernel.hip", "paper_2409_19156_amd/csrc/zp_internal.hpp"),
-           "sha256": "065da48cd6ee87393c9dc0aac905c5fea11ba878e7e1b021cf18dce53efef03f",
-           "fetch_kib": 468.5, "fetch_scale": 1048576.0 / 524299.5,
-           "write_kib": 424768.0, "write_scale": 1.0}
+           "sha256": "3a57c2c967d0012d97e8508ab1e3eae43f26d23c1440cfc79c5f75ec5123ffa2",
+           "fetch_kib": 469.0, "fetch_scale": 1048576.0 / 524299.8,
+           "write_kib": 424769.9, "write_scale": 1.0}
 
 
 def measured_traffic():
@@ -534,7 +534,7 @@ def main():
                    "modes": wl.M, "points": wl.P, "outputs": 5, "entries": entries},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "chain_kernel<3, true, false, 2, false, false>", "bytes_per_launch": bytes_per_launch,
+                     "kernel": "chain_kernel<3, true, false, 2, false, false, false>", "bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": ms * 1e3, "measured_fill_GBs": fill_gbs, "fill_GBs": fill_rates,
                      "frac_of_measured_fill": achieved / fill_gbs},
         "basis_polar": {"entry": "zp_basis_polar (64 radii x 128 angles, same output)", "ms": ms_polar,
