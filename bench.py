@@ -539,7 +539,8 @@ def main():
                      "frac_of_measured_fill": achieved / fill_gbs},
         "basis_polar": {"entry": "zp_basis_polar (64 radii x 128 angles, same output)", "ms": ms_polar,
                         "entries_per_s": entries / (ms_polar * 1e-3),
-                        "frac_of_hbm_peak": bytes_per_launch / (ms_polar * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                        "frac_of_hbm_peak": bytes_per_launch / (ms_polar * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        "frac_of_measured_fill": bytes_per_launch / (ms_polar * 1e-3) / 1e9 / fill_gbs},
         "first_call_ms": first_call_ms,
         "timed_wall_ms": wall_ms,
     }
@@ -550,6 +551,8 @@ def main():
         res["spectral3d"] = spectral3d_leg(steps=max(3, min(args.steps, 10)), warmup=2)
     if not args.no_radial:
         res["radial"] = radial_legs(steps=max(3, min(args.steps, 10)), warmup=2)
+        for leg in res["radial"].values():  # against the write rate measured above as well
+            leg["frac_of_measured_fill"] = leg["GBs"] / fill_gbs
     if not args.no_ad:
         res["ad_analysis"] = ad_analysis_leg(steps=max(3, min(args.steps, 5)), warmup=1)
     if not args.no_cpu_baseline:
