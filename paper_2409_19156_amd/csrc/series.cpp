@@ -57,7 +57,13 @@ struct CacheLayout {
 
 // Split-K count for grad_c: enough workgroups to fill the chip several times,
 // preferring a count that is a whole number of waves over the 256 CUs (one
-// workgroup per CU at a time), each split a whole number of pads.
+// workgroup per CU at a time), each split a whole number of pads and at least
+// kMinSplitPads of them: shorter splits spend more on writing and reducing
+// their partial sums than they gain in parallelism (n <= 64 on 8192 points:
+// 32 -> 8 splits made forward + backward 3-12% faster; n <= 40 on 16384
+// points: 64 -> 16 splits, 2%).
+constexpr int64_t kMinSplitPads = 8;
+
 int splits_for(int64_t M, int64_t B, int64_t Kp, int ct)
 {
     (void)ct;
@@ -67,6 +73,7 @@ int splits_for(int64_t M, int64_t B, int64_t Kp, int ct)
     double best_eff = 0.0;
     for (int64_t s = 1; s <= units && s <= 64; ++s) {
         if (units % s) continue;
+        if (s > 1 && units / s < kMinSplitPads) break;
         const int64_t wgs = tiles * s;
         const double waves = (double)wgs / 256.0;
         const double eff = waves / std::ceil(waves);   // occupancy of the last wave
