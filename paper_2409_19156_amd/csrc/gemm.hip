@@ -237,10 +237,22 @@ template <> struct Cfg<CT_BF3> {
     static constexpr int BM = 128, BN = 128, BK = 32, WM = 64, WN = 32;
 };
 
+// The FP32 split-K and column-dot contractions use 64 x 16 wave tiles (a
+// 128 x 64 workgroup tile): half the accumulators, so that they fit the
+// 128-register build (gemm_kernel_w4) and two workgroups share a CU.  FP32
+// operands need few LDS bytes per product, so the narrower tiles cost little
+// there; the forward keeps 64 x 32 (narrow, it measured 6% slower).
+template <int CT, int EPI> struct CfgE : Cfg<CT> {
+    static constexpr bool NARROW = CT == CT_F32 && EPI != EPI_STORE;
+    static constexpr int BN = NARROW ? 64 : Cfg<CT>::BN;
+    static constexpr int WN = NARROW ? 16 : Cfg<CT>::WN;
+    static constexpr bool W4 = CT == CT_F64 || NARROW; // compiled for four waves per SIMD
+};
+
 template <int CT, int ALAY, int BLAY, int EPI, int NSET>
 __device__ __forceinline__ void gemm_body(const GemmDesc &g)
 {
-    using C = Cfg<CT>;
+    using C = CfgE<CT, EPI>;
     constexpr int BM = C::BM, BN = C::BN, BK = C::BK, WM = C::WM, WN = C::WN;
     using TR = CTr<CT>;
     using T = typename TR::T;
@@ -506,8 +518,11 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc g)
 // and one's epilogue and LDS phases overlap the other's products.  Used for
 // every FP64 contraction, where it fits without spills (the column-dot keeps
 // one 8-byte value in scratch across its main loop): forward 6%, split-K 4%
-// and column-dot 18% faster than one workgroup per CU.  The FP32 and bf16
-// instances need 170-220 registers and keep one workgroup per CU.
+// and column-dot 18% faster than one workgroup per CU.  Also for the FP32
+// split-K and column-dot with their narrow tiles (98 and 127 registers): 7%
+// and 9% faster than 64 x 32 wave tiles at one workgroup per CU.  The FP32
+// forward and the bf16 instances need 170-220 registers and keep one
+// workgroup per CU.
 template <int CT, int ALAY, int BLAY, int EPI>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void gemm_kernel_w4(GemmDesc g)
 {
@@ -517,10 +532,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
 template <int CT, int ALAY, int BLAY, int EPI>
 hipError_t launch_t(const GemmDesc &g, hipStream_t s)
 {
-    using C = Cfg<CT>;
+    using C = CfgE<CT, EPI>;
     const dim3 grid((unsigned)((g.M + C::BM - 1) / C::BM), (unsigned)((g.N + C::BN - 1) / C::BN),
                     (unsigned)g.splits);
-    if constexpr (CT == CT_F64)
+    if constexpr (C::W4)
         hipLaunchKernelGGL((gemm_kernel_w4<CT, ALAY, BLAY, EPI>), grid, dim3(kThreads), 0, s, g);
     else
         hipLaunchKernelGGL((gemm_kernel<CT, ALAY, BLAY, EPI>), grid, dim3(kThreads), 0, s, g);
