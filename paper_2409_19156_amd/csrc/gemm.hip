@@ -237,22 +237,26 @@ template <> struct Cfg<CT_BF3> {
     static constexpr int BM = 128, BN = 128, BK = 32, WM = 64, WN = 32;
 };
 
-// The FP32 split-K and column-dot contractions use 64 x 16 wave tiles (a
-// 128 x 64 workgroup tile): half the accumulators, so that they fit the
-// 128-register build (gemm_kernel_w4) and two workgroups share a CU.  FP32
-// operands need few LDS bytes per product, so the narrower tiles cost little
-// there; the forward keeps 64 x 32 (narrow, it measured 6% slower).
-template <int CT, int EPI> struct CfgE : Cfg<CT> {
-    static constexpr bool NARROW = CT == CT_F32 && EPI != EPI_STORE;
+// Narrow shape: 64 x 16 wave tiles (a 128 x 64 workgroup tile), half the
+// accumulators of 64 x 32.  The FP32 split-K and column-dot always take it, so
+// that they fit the 128-register build (gemm_kernel_w4) and two workgroups
+// share a CU; FP32 operands need few LDS bytes per product, so the narrower
+// tiles cost little there (the FP32 forward, narrow, measured 6% slower).  The
+// FP64 split-K and column-dot take it on small problems (below), where twice
+// the workgroups fill the chip better.
+template <int CT, int EPI> constexpr bool kNarrowDefault = CT == CT_F32 && EPI != EPI_STORE;
+
+template <int CT, int EPI, bool NARROW_ = kNarrowDefault<CT, EPI>> struct CfgE : Cfg<CT> {
+    static constexpr bool NARROW = NARROW_;
     static constexpr int BN = NARROW ? 64 : Cfg<CT>::BN;
     static constexpr int WN = NARROW ? 16 : Cfg<CT>::WN;
     static constexpr bool W4 = CT == CT_F64 || NARROW; // compiled for four waves per SIMD
 };
 
-template <int CT, int ALAY, int BLAY, int EPI, int NSET>
+template <int CT, int ALAY, int BLAY, int EPI, int NSET, bool NARROW>
 __device__ __forceinline__ void gemm_body(const GemmDesc &g)
 {
-    using C = CfgE<CT, EPI>;
+    using C = CfgE<CT, EPI, NARROW>;
     constexpr int BM = C::BM, BN = C::BN, BK = C::BK, WM = C::WM, WN = C::WN;
     using TR = CTr<CT>;
     using T = typename TR::T;
@@ -510,7 +514,7 @@ __device__ __forceinline__ void gemm_body(const GemmDesc &g)
 template <int CT, int ALAY, int BLAY, int EPI>
 __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc g)
 {
-    gemm_body<CT, ALAY, BLAY, EPI, 2>(g);
+    gemm_body<CT, ALAY, BLAY, EPI, 2, kNarrowDefault<CT, EPI>>(g);
 }
 
 // The same kernel compiled for four waves per SIMD (at most 128 registers,
@@ -523,23 +527,37 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc g)
 // and 9% faster than 64 x 32 wave tiles at one workgroup per CU.  The FP32
 // forward and the bf16 instances need 170-220 registers and keep one
 // workgroup per CU.
-template <int CT, int ALAY, int BLAY, int EPI>
+template <int CT, int ALAY, int BLAY, int EPI, bool NARROW>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void gemm_kernel_w4(GemmDesc g)
 {
-    gemm_body<CT, ALAY, BLAY, EPI, 1>(g);
+    gemm_body<CT, ALAY, BLAY, EPI, 1, NARROW>(g);
 }
 
-template <int CT, int ALAY, int BLAY, int EPI>
-hipError_t launch_t(const GemmDesc &g, hipStream_t s)
+template <int CT, int ALAY, int BLAY, int EPI, bool NARROW>
+hipError_t launch_shape(const GemmDesc &g, hipStream_t s)
 {
-    using C = CfgE<CT, EPI>;
+    using C = CfgE<CT, EPI, NARROW>;
     const dim3 grid((unsigned)((g.M + C::BM - 1) / C::BM), (unsigned)((g.N + C::BN - 1) / C::BN),
                     (unsigned)g.splits);
     if constexpr (C::W4)
-        hipLaunchKernelGGL((gemm_kernel_w4<CT, ALAY, BLAY, EPI>), grid, dim3(kThreads), 0, s, g);
+        hipLaunchKernelGGL((gemm_kernel_w4<CT, ALAY, BLAY, EPI, NARROW>), grid, dim3(kThreads), 0, s, g);
     else
         hipLaunchKernelGGL((gemm_kernel<CT, ALAY, BLAY, EPI>), grid, dim3(kThreads), 0, s, g);
     return hipGetLastError();
+}
+
+// FP64 split-K and column-dot: the narrow shape when the wide tiles give fewer
+// than four workgroups per CU (n <= 40 series, 861 modes x 16 384 points x 256
+// sets: forward + backward 0.54 -> 0.50 ms); larger problems keep the wide
+// tiles (n <= 64 on 65 536 points was 2% slower narrow).
+template <int CT, int ALAY, int BLAY, int EPI>
+hipError_t launch_t(const GemmDesc &g, hipStream_t s)
+{
+    if constexpr (CT == CT_F64 && EPI != EPI_STORE) {
+        const int64_t wide = ((g.M + 127) / 128) * ((g.N + 127) / 128) * (int64_t)g.splits;
+        if (wide < 4 * (int64_t)device_cus()) return launch_shape<CT, ALAY, BLAY, EPI, true>(g, s);
+    }
+    return launch_shape<CT, ALAY, BLAY, EPI, kNarrowDefault<CT, EPI>>(g, s);
 }
 
 // The operand-layout combinations the series uses (anything else is an

@@ -23,6 +23,19 @@
 #include "series.hpp"
 
 namespace zp {
+
+int device_cus()
+{
+    static std::mutex mu;
+    static int cus[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!cus[dev] && hipDeviceGetAttribute(&cus[dev], hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus[dev] = 0;
+    return cus[dev];
+}
+
 zp_status check_modes_arg(const int32_t *n, const int32_t *m, int64_t M);
 }
 
@@ -198,18 +211,6 @@ hipStream_t helper_stream()
     return streams[dev];
 }
 
-// Compute units of the current device (cached per device; 0 if unknown).
-int device_cus()
-{
-    static std::mutex mu;
-    static int cus[64] = {};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-    std::lock_guard<std::mutex> lock(mu);
-    if (!cus[dev] && hipDeviceGetAttribute(&cus[dev], hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        cus[dev] = 0;
-    return cus[dev];
-}
 
 // Forward pipeline: chunks of points alternate between the caller's stream
 // and the helper stream; chunk i+1's basis starts when chunk i's basis has

@@ -64,6 +64,9 @@ int coldot_bm(int ct);
 
 zp_status launch_gemm(const GemmDesc &g, hipStream_t s);
 
+// Compute units of the current device (cached per device; 0 if unknown).
+int device_cus();
+
 // Series forward pieces shared by zp_series_fwd and its allocation-free
 // variant: argument checks (ZP_OK also for the M, P or B == 0 no-op), the
 // smallest workspace without a cache, and the work itself for a plan whose
