@@ -2,12 +2,13 @@
 // conversion and fixed-order reduction kernels around them.
 //
 // C(i,j) = sum_k A(i,k) B(k,j) with a 512-thread workgroup (2 x 4 waves) per
-// BM x BN output tile.  Operands come from zero-padded buffers (every
+// BM x BN output tile (128 x 128, or 128 x 64 with the narrow shape below).  Operands come from zero-padded buffers (every
 // dimension a multiple of kPad), so tile loads need no bounds checks; stores
 // are masked to the true output size.  Each operand tile is copied into LDS
 // in its global layout (k-contiguous rows, or rows along the other index),
 // with a row swizzle or padding that keeps the MFMA fragment reads and the
-// tile stores free of bank conflicts; the fragment reads follow the layout.  The bf16 path needs
+// tile stores free of bank conflicts; the fragment reads follow the layout.
+// The bf16 path needs
 // eight consecutive k per lane, so an operand that is not k-contiguous in
 // memory is transposed while it is written to LDS.  Tiles are double
 // buffered: the next tile's global loads are in flight during the current
@@ -47,8 +48,9 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 512; // eight waves per workgroup
-// Flush interval (k terms) of the FP32 accumulators: every 16 k for FP32 (four
-// x4 products), every k step of 32 for bf16 x 3 (one bf16 product of depth 32
+// Flush interval (k terms) of the FP32 accumulators: every 16 k for the FP32
+// column-dot and every 32 k for the other FP32 contractions (four or eight x4
+// products), every k step of 32 for bf16 x 3 (one bf16 product of depth 32
 // per cross term).  Sums that cancel after the contraction amplify its
 // rounding errors: the column-dot epilogue sums the product weighted by basis
 // derivatives over the modes, and the three-dimensional series folds partial
