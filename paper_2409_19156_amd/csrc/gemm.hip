@@ -2,15 +2,15 @@
 // conversion and fixed-order reduction kernels around them.
 //
 // C(i,j) = sum_k A(i,k) B(k,j) with a 512-thread workgroup (2 x 4 waves) per
-// BM x BN output tile (128 x 128, or 128 x 64 with the narrow shape below).  Operands come from zero-padded buffers (every
-// dimension a multiple of kPad), so tile loads need no bounds checks; stores
-// are masked to the true output size.  Each operand tile is copied into LDS
-// in its global layout (k-contiguous rows, or rows along the other index),
-// with a row swizzle or padding that keeps the MFMA fragment reads and the
-// tile stores free of bank conflicts; the fragment reads follow the layout.
-// The bf16 path needs
-// eight consecutive k per lane, so an operand that is not k-contiguous in
-// memory is transposed while it is written to LDS.  Tiles are double
+// BM x BN output tile (128 x 128, or 128 x 64 with the narrow shape below).
+// Operands come from zero-padded buffers (every dimension a multiple of
+// kPad), so tile loads need no bounds checks; stores are masked to the true
+// output size.  Each operand tile is copied into LDS in its global layout
+// (k-contiguous rows, or rows along the other index), with a row swizzle or
+// padding that keeps the MFMA fragment reads and the tile stores free of bank
+// conflicts; the fragment reads follow the layout.  The bf16 path needs eight
+// consecutive k per lane, so an operand that is not k-contiguous in memory is
+// transposed while it is written to LDS.  Tiles are double
 // buffered: the next tile's global loads are in flight during the current
 // tile's MFMAs.
 //
