@@ -262,8 +262,12 @@ __device__ __forceinline__ void gemm_body(const GemmDesc &g)
     constexpr int BM = C::BM, BN = C::BN, BK = C::BK, WM = C::WM, WN = C::WN;
     using TR = CTr<CT>;
     using T = typename TR::T;
+    // B in MFMA fragment order (bf16 only) is loaded from global memory into
+    // registers a k step ahead and skips LDS.
+    constexpr bool BFRAG = BLAY == LAY_FRAG;
+    static_assert(!BFRAG || CT == CT_BF3, "fragment-order operands are bf16");
     using TA = Tile<CT, BM, BK, ALAY>;
-    using TB = Tile<CT, BN, BK, BLAY>;
+    using TB = Tile<CT, BN, BK, BFRAG ? LAY_KC : BLAY>;
     constexpr int NP = TR::NP;
     constexpr int FM = WM / 16, FN = WN / 16;
     constexpr bool MIXED = CT != CT_F64;
@@ -271,7 +275,7 @@ __device__ __forceinline__ void gemm_body(const GemmDesc &g)
     static_assert(CT != CT_BF3 || kFlush<CT, EPI> == BK, "bf16 steps alternate the sign of B: flush every step");
 
     __shared__ __attribute__((aligned(16))) T As[2][NP * TA::ELEMS];
-    __shared__ __attribute__((aligned(16))) T Bs[2][NP * TB::ELEMS];
+    __shared__ __attribute__((aligned(16))) T Bs[2][BFRAG ? 8 : NP * TB::ELEMS];
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -347,16 +351,32 @@ __device__ __forceinline__ void gemm_body(const GemmDesc &g)
     // t+2 into the same registers): 8 to 16 fewer registers, for the builds
     // capped at 128.
     typename TA::Regs ra[NSET];
-    typename TB::Regs rb[NSET];
+    typename TB::Regs rb[BFRAG ? 1 : NSET];
+    // fragment-order B: this wave's FN x 3 fragments of k step t
+    bf8 fbr[2][BFRAG ? FN : 1][3];
+    auto load_bfrag = [&](int t, bf8(&dst)[BFRAG ? FN : 1][3]) {
+        if constexpr (BFRAG) {
+            const int64_t blk = (kbeg / BK + t) * b_ld + (j0 + wn0) / 16;
+#pragma unroll
+            for (int b = 0; b < FN; ++b)
+#pragma unroll
+                for (int p = 0; p < 3; ++p)
+                    dst[b][p] = *(const bf8 *)((const uint16_t *)g.b.base + p * b_sub + ((blk + b) * 64 + lane) * 8);
+        }
+    };
     if (ntiles > 0) {
         TA::load(ra[0], a_base, a_ld, a_sub, i0, kbeg);
-        TB::load(rb[0], b_base, b_ld, b_sub, j0, kbeg);
         TA::store(ra[0], As[0]);
-        TB::store(rb[0], Bs[0]);
+        if constexpr (BFRAG) {
+            load_bfrag(0, fbr[0]);
+        } else {
+            TB::load(rb[0], b_base, b_ld, b_sub, j0, kbeg);
+            TB::store(rb[0], Bs[0]);
+        }
     }
     if (ntiles > 1) {
         TA::load(ra[NSET - 1], a_base, a_ld, a_sub, i0, kbeg + BK);
-        TB::load(rb[NSET - 1], b_base, b_ld, b_sub, j0, kbeg + BK);
+        if constexpr (!BFRAG) TB::load(rb[NSET - 1], b_base, b_ld, b_sub, j0, kbeg + BK);
     }
     __syncthreads();
 
@@ -365,11 +385,14 @@ __device__ __forceinline__ void gemm_body(const GemmDesc &g)
         constexpr int cur = decltype(cur_c)::value;
         if (t + 1 < ntiles) {
             TA::store(ra[(cur ^ 1) % NSET], As[cur ^ 1]);
-            TB::store(rb[(cur ^ 1) % NSET], Bs[cur ^ 1]);
+            if constexpr (BFRAG)
+                load_bfrag(t + 1, fbr[cur ^ 1]);
+            else
+                TB::store(rb[(cur ^ 1) % NSET], Bs[cur ^ 1]);
         }
         if (t + 2 < ntiles) {
             TA::load(ra[cur % NSET], a_base, a_ld, a_sub, i0, kbeg + (int64_t)(t + 2) * BK);
-            TB::load(rb[cur % NSET], b_base, b_ld, b_sub, j0, kbeg + (int64_t)(t + 2) * BK);
+            if constexpr (!BFRAG) TB::load(rb[cur % NSET], b_base, b_ld, b_sub, j0, kbeg + (int64_t)(t + 2) * BK);
         }
         const T *LA = As[cur];
         const T *LB = Bs[cur];
@@ -386,8 +409,12 @@ __device__ __forceinline__ void gemm_body(const GemmDesc &g)
                 for (int b = 0; b < FN; ++b) {
                     bf8 fb[3];
 #pragma unroll
-                    for (int p = 0; p < 3; ++p)
-                        fb[p] = *(const bf8 *)(LB + p * TB::ELEMS + TB::at(wn0 + b * 16 + lx, kk + 8 * lk));
+                    for (int p = 0; p < 3; ++p) {
+                        if constexpr (BFRAG)
+                            fb[p] = fbr[cur][b][p];
+                        else
+                            fb[p] = *(const bf8 *)(LB + p * TB::ELEMS + TB::at(wn0 + b * 16 + lx, kk + 8 * lk));
+                    }
                     if constexpr (cur == 1) // odd steps: -B (see the flush)
 #pragma unroll
                         for (int p = 0; p < 3; ++p)
@@ -571,6 +598,7 @@ hipError_t launch_e(const GemmDesc &g, hipStream_t s)
     if constexpr (EPI == EPI_STORE) {
         if constexpr (CT == CT_BF3) {
             if (a == LAY_KB8 && b == LAY_KC) return launch_t<CT, LAY_KB8, LAY_KC, EPI>(g, s);
+            if (a == LAY_KB8 && b == LAY_FRAG) return launch_t<CT, LAY_KB8, LAY_FRAG, EPI>(g, s);
         } else {
             if (a == LAY_XC && b == LAY_XC) return launch_t<CT, LAY_XC, LAY_XC, EPI>(g, s);
         }
@@ -747,6 +775,38 @@ __global__ __launch_bounds__(256) void convert_gather_t_kernel(const double *__r
     }
 }
 
+// One lane per (column x, group of 8 k): eight values gathered through perm
+// (consecutive lanes read consecutive columns), split into the three bf16
+// planes as put() does, and written as one 16-byte fragment row per plane.
+__global__ __launch_bounds__(256) void convert_gather_frag_kernel(const double *__restrict__ src,
+                                                                  const int32_t *__restrict__ perm, int64_t R,
+                                                                  int64_t C, int64_t lds, uint16_t *dst, int64_t xpad,
+                                                                  int64_t sub)
+{
+    const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t kg = blockIdx.y; // k = 8 kg .. 8 kg + 7
+    if (x >= xpad) return;
+    u4 w[3] = {};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int64_t k = kg * 8 + e;
+        const double v = (k < R && x < C) ? src[(int64_t)perm[k] * lds + x] : 0.0;
+        const uint16_t h = bf16_rne((float)v);
+        const double r1 = v - bf16_val(h);
+        const uint16_t m = bf16_rne((float)r1);
+        const double r2 = r1 - bf16_val(m);
+        const uint16_t l = bf16_rne((float)r2);
+        const int q = e >> 1, sh = (e & 1) * 16;
+        w[0][q] |= (uint32_t)h << sh;
+        w[1][q] |= (uint32_t)m << sh;
+        w[2][q] |= (uint32_t)l << sh;
+    }
+    const int64_t lane = (kg & 3) * 16 + (x & 15);
+    const int64_t off = (((kg >> 2) * (xpad / 16) + (x >> 4)) * 64 + lane) * 8;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) *(u4 *)(dst + p * sub + off) = w[p];
+}
+
 // Zero the pad of a k-blocked bf16 operand [Mp/8][ld][8] (three planes, sub
 // apart): every mode e >= M and every point p >= P.
 __global__ void zero_kb8_kernel(uint16_t *dst, int64_t M, int64_t Mp, int64_t P, int64_t ld, int64_t sub)
@@ -872,6 +932,15 @@ zp_status launch_convert_gather_t(const double *src, const int32_t *perm, int64_
 {
     const dim3 grid((unsigned)(ncols / 32), (unsigned)(rows_pad / 32));
     hipLaunchKernelGGL(convert_gather_t_kernel, grid, dim3(256), 0, s, src, perm, R, C, lds, ct, dst, ldd, sub);
+    return hip_check(hipGetLastError(), "convert launch");
+}
+
+zp_status launch_convert_gather_frag(const double *src, const int32_t *perm, int64_t R, int64_t C, int64_t lds,
+                                     void *dst, int64_t xpad, int64_t kpad, int64_t sub, hipStream_t s)
+{
+    const dim3 grid((unsigned)((xpad + 255) / 256), (unsigned)(kpad / 8));
+    hipLaunchKernelGGL(convert_gather_frag_kernel, grid, dim3(256), 0, s, src, perm, R, C, lds, (uint16_t *)dst, xpad,
+                       sub);
     return hip_check(hipGetLastError(), "convert launch");
 }
 

@@ -389,8 +389,8 @@ zp_status series_fwd_run(const Plan &pl, int64_t M, const double *d_r, const dou
     char *ws = (char *)d_ws;
     const int64_t Mp = L.Mp, Bp = L.Bp;
     void *cbuf = ws + L.c_off;
-    if (ct == CT_BF3) // B(k = e, j = b) = c[perm[e]][b], k-contiguous
-        st = launch_convert_gather_t(d_c, plan->d_perm, M, B, B, ct, cbuf, Mp, Bp, Bp * Mp, Mp, s);
+    if (ct == CT_BF3) // B(k = e, j = b) = c[perm[e]][b], in MFMA fragment order
+        st = launch_convert_gather_frag(d_c, plan->d_perm, M, B, B, cbuf, Bp, Mp, Bp * Mp, s);
     else // B(k = q, j = b) = c[q][b]
         st = launch_convert(d_c, M, B, B, ct, cbuf, Bp, Mp, Mp * Bp, false, s);
     if (st != ZP_OK) return st;
@@ -450,7 +450,7 @@ zp_status series_fwd_run(const Plan &pl, int64_t M, const double *d_r, const dou
         g.ct = ct;
         if (ct == CT_BF3) {
             g.a = Operand{zb, pcp, Mp * pcp, LAY_KB8}; // A(i = p, k = e)
-            g.b = Operand{cbuf, Mp, Bp * Mp, LAY_KC};            // B(k = e, j = b)
+            g.b = Operand{cbuf, Bp / 16, Bp * Mp, LAY_FRAG};     // B(k = e, j = b)
         } else if (have_cache) {
             g.a = Operand{cache + CL.z_off + zsz * (size_t)p0, CL.Pp, Mp * CL.Pp, LAY_XC}; // A(i = p, k = q) = Z[q][p]
             g.b = Operand{cbuf, Bp, Mp * Bp, LAY_XC};

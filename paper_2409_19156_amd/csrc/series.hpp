@@ -24,7 +24,7 @@ inline int64_t pad_up(int64_t x) { return (x + kPad - 1) / kPad * kPad; }
 //   LAY_KB8 : base[((k/8)*ld + x)*8 + k%8]        (k in blocks of eight)
 //   LAY_KC32: as LAY_KC, but FP32 values of a BF3 operand; the GEMM splits
 //             them into the three bf16 planes on the way into LDS
-enum Layout : int { LAY_KC = 0, LAY_XC = 1, LAY_KB8 = 2, LAY_KC32 = 3 };
+enum Layout : int { LAY_KC = 0, LAY_XC = 1, LAY_KB8 = 2, LAY_KC32 = 3, LAY_FRAG = 4 };
 
 // Operand of C(i,j) = sum_k A(i,k) B(k,j); `sub` separates the BF3 planes.
 struct Operand {
@@ -92,6 +92,12 @@ zp_status launch_convert_both(const double *src, int64_t R, int64_t C, int64_t l
 
 // dst[c][e] = src[perm[e]][c] (e < R, zero padded) for columns e < ncols of
 // dst [rows_pad][ldd] (ncols a multiple of 32, <= ldd).
+// bf16 x 3 operand in MFMA fragment order for B(k = e, j = x) = src[perm[e]][x]:
+// per k step of 32 and block of 16 columns, 64 lanes x 8 bf16 contiguous (lane
+// = 16 (k % 32 / 8) + x % 16), blocks along x fastest (xblocks = xpad / 16);
+// three planes sub apart; zero outside R x C.
+zp_status launch_convert_gather_frag(const double *src, const int32_t *perm, int64_t R, int64_t C, int64_t lds,
+                                     void *dst, int64_t xpad, int64_t kpad, int64_t sub, hipStream_t s);
 zp_status launch_convert_gather_t(const double *src, const int32_t *perm, int64_t R, int64_t C, int64_t lds,
                                   int ct, void *dst, int64_t ldd, int64_t rows_pad, int64_t sub, int64_t ncols,
                                   hipStream_t s);
