@@ -605,6 +605,7 @@ hipError_t launch_e(const GemmDesc &g, hipStream_t s)
     } else if constexpr (EPI == EPI_PARTIAL) {
         if constexpr (CT == CT_BF3) {
             if (a == LAY_KC32 && b == LAY_KC) return launch_t<CT, LAY_KC32, LAY_KC, EPI>(g, s);
+            if (a == LAY_KC32 && b == LAY_FRAG) return launch_t<CT, LAY_KC32, LAY_FRAG, EPI>(g, s);
         } else {
             if (a == LAY_KC && b == LAY_XC) return launch_t<CT, LAY_KC, LAY_XC, EPI>(g, s);
         }
@@ -775,6 +776,34 @@ __global__ __launch_bounds__(256) void convert_gather_t_kernel(const double *__r
     }
 }
 
+// FP64 value -> three bf16 planes, the same split as put()
+__device__ __forceinline__ void split3d(double v, uint32_t &h, uint32_t &m, uint32_t &l)
+{
+    h = bf16_rne((float)v);
+    const double r1 = v - bf16_val((uint16_t)h);
+    m = bf16_rne((float)r1);
+    const double r2 = r1 - bf16_val((uint16_t)m);
+    l = bf16_rne((float)r2);
+}
+
+// Eight values (k = 8 kg .. 8 kg + 7 of one column) -> one 16-byte fragment
+// row per plane at element offset off.
+__device__ __forceinline__ void put_frag8(uint16_t *dst, int64_t sub, int64_t off, const double (&v)[8])
+{
+    u4 w[3] = {};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        uint32_t h, m, l;
+        split3d(v[e], h, m, l);
+        const int q = e >> 1, sh = (e & 1) * 16;
+        w[0][q] |= h << sh;
+        w[1][q] |= m << sh;
+        w[2][q] |= l << sh;
+    }
+#pragma unroll
+    for (int p = 0; p < 3; ++p) *(u4 *)(dst + p * sub + off) = w[p];
+}
+
 // One lane per (column x, group of 8 k): eight values gathered through perm
 // (consecutive lanes read consecutive columns), split into the three bf16
 // planes as put() does, and written as one 16-byte fragment row per plane.
@@ -786,25 +815,47 @@ __global__ __launch_bounds__(256) void convert_gather_frag_kernel(const double *
     const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t kg = blockIdx.y; // k = 8 kg .. 8 kg + 7
     if (x >= xpad) return;
-    u4 w[3] = {};
+    double v[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int64_t k = kg * 8 + e;
-        const double v = (k < R && x < C) ? src[(int64_t)perm[k] * lds + x] : 0.0;
-        const uint16_t h = bf16_rne((float)v);
-        const double r1 = v - bf16_val(h);
-        const uint16_t m = bf16_rne((float)r1);
-        const double r2 = r1 - bf16_val(m);
-        const uint16_t l = bf16_rne((float)r2);
-        const int q = e >> 1, sh = (e & 1) * 16;
-        w[0][q] |= (uint32_t)h << sh;
-        w[1][q] |= (uint32_t)m << sh;
-        w[2][q] |= (uint32_t)l << sh;
+        v[e] = (k < R && x < C) ? src[(int64_t)perm[k] * lds + x] : 0.0;
     }
     const int64_t lane = (kg & 3) * 16 + (x & 15);
-    const int64_t off = (((kg >> 2) * (xpad / 16) + (x >> 4)) * 64 + lane) * 8;
+    put_frag8(dst, sub, (((kg >> 2) * (xpad / 16) + (x >> 4)) * 64 + lane) * 8, v);
+}
+
+// The upstream gradient g [R][C] (points x sets) as the two bf16 x 3 operands
+// of the backward, from one read of each 32 x 64 tile: [points][sets]
+// k-contiguous for the column-dot's B(k = set, j = point) (dst_c, rows of
+// xpad_c) and, if dst_s is set, MFMA fragment order for the split-K's
+// B(k = point, j = set) (xpad_c / 16 column blocks).  Zero outside R x C.
+__global__ __launch_bounds__(256) void convert_g_bwd_kernel(const double *__restrict__ src, int64_t R, int64_t C,
+                                                            int64_t lds, uint16_t *dst_c, int64_t subc,
+                                                            uint16_t *dst_s, int64_t subs, int64_t xpad_c)
+{
+    __shared__ double tile[32][65];
+    const int64_t r0 = (int64_t)blockIdx.x * 32, c0 = (int64_t)blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int y = ty; y < 32; y += 4) {
+        const int64_t r = r0 + y, c = c0 + tx;
+        tile[y][tx] = (r < R && c < C) ? src[r * lds + c] : 0.0;
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    double v[8];
+    { // column-dot operand: row r0 + t / 8, sets c0 + 8 (t % 8) ..; eight lanes per 128-byte row
+        const int row = t >> 3, q = t & 7;
 #pragma unroll
-    for (int p = 0; p < 3; ++p) *(u4 *)(dst + p * sub + off) = w[p];
+        for (int e = 0; e < 8; ++e) v[e] = tile[row][q * 8 + e];
+        put_frag8(dst_c, subc, (r0 + row) * xpad_c + c0 + q * 8, v);
+    }
+    if (dst_s) { // split-K operand: set c0 + 16 (t / 64) + t % 16, points r0 + 8 ((t % 64) / 16) ..
+        const int bb = t >> 6, lane = t & 63, kg = lane >> 4, xl = lane & 15;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = tile[kg * 8 + e][bb * 16 + xl];
+        put_frag8(dst_s, subs, (((r0 / 32) * (xpad_c / 16) + c0 / 16 + bb) * 64 + lane) * 8, v);
+    }
 }
 
 // Zero the pad of a k-blocked bf16 operand [Mp/8][ld][8] (three planes, sub
@@ -941,6 +992,15 @@ zp_status launch_convert_gather_frag(const double *src, const int32_t *perm, int
     const dim3 grid((unsigned)((xpad + 255) / 256), (unsigned)(kpad / 8));
     hipLaunchKernelGGL(convert_gather_frag_kernel, grid, dim3(256), 0, s, src, perm, R, C, lds, (uint16_t *)dst, xpad,
                        sub);
+    return hip_check(hipGetLastError(), "convert launch");
+}
+
+zp_status launch_convert_g_bwd(const double *src, int64_t R, int64_t C, int64_t lds, void *dst_c, int64_t subc,
+                               void *dst_s, int64_t subs, int64_t xpad_r, int64_t xpad_c, hipStream_t s)
+{
+    const dim3 grid((unsigned)(xpad_r / 32), (unsigned)(xpad_c / 64));
+    hipLaunchKernelGGL(convert_g_bwd_kernel, grid, dim3(256), 0, s, src, R, C, lds, (uint16_t *)dst_c, subc,
+                       (uint16_t *)dst_s, subs, xpad_c);
     return hip_check(hipGetLastError(), "convert launch");
 }
 

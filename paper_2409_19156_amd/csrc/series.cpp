@@ -562,9 +562,9 @@ zp_status zp_series_bwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
         // has that layout and is read in place.
         const bool g_in_place = ct == CT_F64 && B == Bp && pc == pcp && ((uintptr_t)d_g & 15) == 0;
         const void *gbuf = g_in_place ? (const void *)(d_g + p0 * B) : (const void *)(ws + L.g_off);
-        if (ct == CT_BF3 && d_grad_c) { // both layouts from one read of g
-            st = launch_convert_both(d_g + p0 * B, pc, B, B, ct, ws + L.g_off, Bp, pcp * Bp, ws + L.gt_off, pcp,
-                                     Bp * pcp, s);
+        if (ct == CT_BF3) { // both contractions' operands from one read of g
+            st = launch_convert_g_bwd(d_g + p0 * B, pc, B, B, ws + L.g_off, pcp * Bp,
+                                      d_grad_c ? ws + L.gt_off : nullptr, Bp * pcp, pcp, Bp, s);
             if (st != ZP_OK) return st;
         } else if (!g_in_place) {
             st = launch_convert(d_g + p0 * B, pc, B, B, ct, ws + L.g_off, Bp, pcp, pcp * Bp, false, s);
@@ -577,7 +577,7 @@ zp_status zp_series_bwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
             g.ct = ct;
             g.a = Operand{z, ldz, zsub, zlay_of(ct)}; // A(i=q, k=p) = Z[q][p]
             if (ct == CT_BF3)
-                g.b = Operand{ws + L.gt_off, pcp, Bp * pcp, LAY_KC}; // B(k=p, j=b) = g^T[b][p]
+                g.b = Operand{ws + L.gt_off, Bp / 16, Bp * pcp, LAY_FRAG}; // B(k=p, j=b) = g[p][b]
             else
                 g.b = Operand{gbuf, Bp, pcp * Bp, LAY_XC}; // B(k=p, j=b) = g[p][b]
             g.M = M;
@@ -597,7 +597,7 @@ zp_status zp_series_bwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
             // over the modes against dZ/dr and dZ/dtheta in the epilogue
             GemmDesc g{};
             g.ct = ct;
-            g.a = Operand{cbuf, Bp, Mp * Bp, LAY_KC};  // A(i=q, k=b) = c[q][b]
+            g.a = Operand{cbuf, Bp, Mp * Bp, LAY_KC}; // A(i=q, k=b) = c[q][b]
             g.b = Operand{gbuf, Bp, pcp * Bp, LAY_KC}; // B(k=b, j=p) = g[p][b]
             g.M = M;
             g.N = pc;

@@ -98,6 +98,13 @@ zp_status launch_convert_both(const double *src, int64_t R, int64_t C, int64_t l
 // three planes sub apart; zero outside R x C.
 zp_status launch_convert_gather_frag(const double *src, const int32_t *perm, int64_t R, int64_t C, int64_t lds,
                                      void *dst, int64_t xpad, int64_t kpad, int64_t sub, hipStream_t s);
+// The upstream gradient g [R][C] (rows = points) as the backward's bf16 x 3
+// operands from one read: [xpad_r][xpad_c] k-contiguous into dst_c (the
+// column-dot's B(k = set, j = point)) and, if dst_s is set, MFMA fragment
+// order into dst_s (the split-K's B(k = point, j = set)); xpad_r, xpad_c are
+// the padded point and set counts (multiples of 32 and 64).
+zp_status launch_convert_g_bwd(const double *src, int64_t R, int64_t C, int64_t lds, void *dst_c, int64_t subc,
+                               void *dst_s, int64_t subs, int64_t xpad_r, int64_t xpad_c, hipStream_t s);
 zp_status launch_convert_gather_t(const double *src, const int32_t *perm, int64_t R, int64_t C, int64_t lds,
                                   int ct, void *dst, int64_t ldd, int64_t rows_pad, int64_t sub, int64_t ncols,
                                   hipStream_t s);
