@@ -597,14 +597,12 @@ hipError_t launch_e(const GemmDesc &g, hipStream_t s)
     const int a = g.a.lay, b = g.b.lay;
     if constexpr (EPI == EPI_STORE) {
         if constexpr (CT == CT_BF3) {
-            if (a == LAY_KB8 && b == LAY_KC) return launch_t<CT, LAY_KB8, LAY_KC, EPI>(g, s);
             if (a == LAY_KB8 && b == LAY_FRAG) return launch_t<CT, LAY_KB8, LAY_FRAG, EPI>(g, s);
         } else {
             if (a == LAY_XC && b == LAY_XC) return launch_t<CT, LAY_XC, LAY_XC, EPI>(g, s);
         }
     } else if constexpr (EPI == EPI_PARTIAL) {
         if constexpr (CT == CT_BF3) {
-            if (a == LAY_KC32 && b == LAY_KC) return launch_t<CT, LAY_KC32, LAY_KC, EPI>(g, s);
             if (a == LAY_KC32 && b == LAY_FRAG) return launch_t<CT, LAY_KC32, LAY_FRAG, EPI>(g, s);
         } else {
             if (a == LAY_KC && b == LAY_XC) return launch_t<CT, LAY_KC, LAY_XC, EPI>(g, s);
@@ -691,12 +689,11 @@ __global__ __launch_bounds__(256) void convert_rows_kernel(const double *__restr
 }
 
 // Transposing conversion through a 64 x 64 LDS tile: dst_t[c][r] = src[r][c]
-// (dst_t [gridDim.y * 64][ldt]), and, if dst_n is not null, the plain copy
-// dst_n[r][c] ([gridDim.x * 64][ldn]) from the same reads.  Zero outside
-// src's R x C; two elements per lane on each store.
+// (dst_t [gridDim.y * 64][ldt]).  Zero outside src's R x C; two elements per
+// lane on each store.
 __global__ __launch_bounds__(256) void convert_t64_kernel(const double *__restrict__ src, int64_t R, int64_t C,
                                                           int64_t lds, int ct, void *dst_t, int64_t ldt,
-                                                          int64_t sub_t, void *dst_n, int64_t ldn, int64_t sub_n)
+                                                          int64_t sub_t)
 {
     __shared__ double tile[64][65];
     const int64_t r0 = (int64_t)blockIdx.x * 64; // src rows = dst_t columns
@@ -711,7 +708,6 @@ __global__ __launch_bounds__(256) void convert_t64_kernel(const double *__restri
         const double v1 = (r < R && c + 1 < C) ? src[r * lds + c + 1] : 0.0;
         tile[y][x] = v0;
         tile[y][x + 1] = v1;
-        if (dst_n) put2(dst_n, ct, r * ldn + c, sub_n, v0, v1);
     }
     __syncthreads();
 #pragma unroll
@@ -750,28 +746,6 @@ __global__ __launch_bounds__(256) void convert_t_kernel(const double *__restrict
     __syncthreads();
     for (int y = ty; y < 32; y += 8) {
         const int64_t c = c0 + y, r = r0 + tx; // dst row c, column r
-        put(dst, ct, c * ldd + r, sub, tile[tx][y]);
-    }
-}
-
-// dst[c][e] = src[perm[e]][c] for e < R (zero beyond), dst [rows_pad][ldd]:
-// the coefficient matrix transposed with its rows taken in chain-major order.
-__global__ __launch_bounds__(256) void convert_gather_t_kernel(const double *__restrict__ src,
-                                                               const int32_t *__restrict__ perm, int64_t R, int64_t C,
-                                                               int64_t lds, int ct, void *dst, int64_t ldd, int64_t sub)
-// (grid.x covers the dst columns written, grid.y the dst rows)
-{
-    __shared__ double tile[32][33];
-    const int64_t r0 = (int64_t)blockIdx.x * 32; // chain-major rows = dst columns
-    const int64_t c0 = (int64_t)blockIdx.y * 32; // src cols = dst rows
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    for (int y = ty; y < 32; y += 8) {
-        const int64_t r = r0 + y, c = c0 + tx;
-        tile[y][tx] = (r < R && c < C) ? src[(int64_t)perm[r] * lds + c] : 0.0;
-    }
-    __syncthreads();
-    for (int y = ty; y < 32; y += 8) {
-        const int64_t c = c0 + y, r = r0 + tx;
         put(dst, ct, c * ldd + r, sub, tile[tx][y]);
     }
 }
@@ -955,34 +929,12 @@ zp_status launch_convert(const double *src, int64_t R, int64_t C, int64_t lds, i
     } else if (ldd % 64 == 0 && rows_pad % 64 == 0 && sub % 2 == 0) {
         // dst is [rows_pad (>= C, padded)][ldd (>= R, padded)]
         const dim3 grid((unsigned)(ldd / 64), (unsigned)(rows_pad / 64));
-        hipLaunchKernelGGL(convert_t64_kernel, grid, dim3(256), 0, s, src, R, C, lds, ct, dst, ldd, sub, (void *)nullptr,
-                           (int64_t)0, (int64_t)0);
+        hipLaunchKernelGGL(convert_t64_kernel, grid, dim3(256), 0, s, src, R, C, lds, ct, dst, ldd, sub);
     } else {
         // both multiples of 32
         const dim3 grid((unsigned)(ldd / 32), (unsigned)(rows_pad / 32));
         hipLaunchKernelGGL(convert_t_kernel, grid, dim3(256), 0, s, src, R, C, lds, ct, dst, ldd, sub);
     }
-    return hip_check(hipGetLastError(), "convert launch");
-}
-
-zp_status launch_convert_both(const double *src, int64_t R, int64_t C, int64_t lds, int ct, void *dst_n, int64_t ldn,
-                              int64_t sub_n, void *dst_t, int64_t ldt, int64_t sub_t, hipStream_t s)
-{
-    // dst_n [ldt][ldn] and dst_t [ldn][ldt]: ldt >= R and ldn >= C, both multiples of 64
-    if (ldt % 64 || ldn % 64 || sub_n % 2 || sub_t % 2 || ((uintptr_t)dst_n & 15) || ((uintptr_t)dst_t & 15))
-        return set_error(ZP_ERR_ARG, "internal: fused conversion needs 64-multiple, aligned operands");
-    const dim3 grid((unsigned)(ldt / 64), (unsigned)(ldn / 64));
-    hipLaunchKernelGGL(convert_t64_kernel, grid, dim3(256), 0, s, src, R, C, lds, ct, dst_t, ldt, sub_t, dst_n, ldn,
-                       sub_n);
-    return hip_check(hipGetLastError(), "convert launch");
-}
-
-zp_status launch_convert_gather_t(const double *src, const int32_t *perm, int64_t R, int64_t C, int64_t lds,
-                                  int ct, void *dst, int64_t ldd, int64_t rows_pad, int64_t sub, int64_t ncols,
-                                  hipStream_t s)
-{
-    const dim3 grid((unsigned)(ncols / 32), (unsigned)(rows_pad / 32));
-    hipLaunchKernelGGL(convert_gather_t_kernel, grid, dim3(256), 0, s, src, perm, R, C, lds, ct, dst, ldd, sub);
     return hip_check(hipGetLastError(), "convert launch");
 }
 

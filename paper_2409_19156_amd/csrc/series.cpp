@@ -663,9 +663,9 @@ extern "C" zp_status zp_series_jvp(const int32_t *h_n, const int32_t *h_m, int64
     for (int which = 0; which < 2; ++which) {
         const double *src = which == 0 ? (with_c ? d_tc : nullptr) : (with_dir ? d_c : nullptr);
         if (!src) continue;
-        if (ct == CT_BF3) // [Bp][K], k contiguous, chain-major order
-            st = launch_convert_gather_t(src, plan->d_perm, M, B, B, ct, cbuf + esz * (size_t)(blk * Mp), K, Bp,
-                                         Bp * K, Mp, s);
+        if (ct == CT_BF3) // chain-major order, MFMA fragment order (block blk: k steps from blk Mp / 32)
+            st = launch_convert_gather_frag(src, plan->d_perm, M, B, B, cbuf + esz * (size_t)(blk * Mp) * (size_t)Bp,
+                                            Bp, Mp, Bp * K, s);
         else // [K][Bp]
             st = launch_convert(src, M, B, B, ct, cbuf + esz * (size_t)(blk * Mp) * (size_t)Bp, Bp, Mp, 0, false, s);
         if (st != ZP_OK) return st;
@@ -721,7 +721,7 @@ extern "C" zp_status zp_series_jvp(const int32_t *h_n, const int32_t *h_m, int64
         g.ct = ct;
         if (ct == CT_BF3) {
             g.a = Operand{zbuf, pcp, K * pcp, LAY_KB8};
-            g.b = Operand{cbuf, K, Bp * K, LAY_KC};
+            g.b = Operand{cbuf, Bp / 16, Bp * K, LAY_FRAG};
         } else {
             g.a = Operand{zbuf, pcp, K * pcp, LAY_XC};
             g.b = Operand{cbuf, Bp, K * Bp, LAY_XC};
@@ -904,13 +904,13 @@ zp_status zp_series_bwd2(const int32_t *h_n, const int32_t *h_m, int64_t M, cons
         }
         st = launch_chain_kernel(*plan, d_r + p0, d_theta + p0, pc, run_e ? 2 : 1, true, o, s);
         if (st != ZP_OK) return st;
-        // the chunk's g: [pcp][Bp] (and [Bp][pcp] for the bf16 dL/dc operand);
-        // read in place in FP64 when it already has that layout
+        // the chunk's g: [pcp][Bp] (and MFMA fragment order for the bf16 dL/dc
+        // operand); read in place in FP64 when it already has that layout
         const bool g_in_place = ct == CT_F64 && B == Bp && pc == pcp && ((uintptr_t)d_g & 15) == 0;
         const void *gbuf = g_in_place ? (const void *)(d_g + p0 * B) : (const void *)(ws + L.g_off);
         if (run_c && ct == CT_BF3) { // both layouts from one read of g
-            st = launch_convert_both(d_g + p0 * B, pc, B, B, ct, ws + L.g_off, Bp, pcp * Bp, ws + L.gt_off, pcp,
-                                     Bp * pcp, s);
+            st = launch_convert_g_bwd(d_g + p0 * B, pc, B, B, ws + L.g_off, pcp * Bp, ws + L.gt_off, Bp * pcp, pcp,
+                                      Bp, s);
             if (st != ZP_OK) return st;
         } else if (!g_in_place) {
             st = launch_convert(d_g + p0 * B, pc, B, B, ct, ws + L.g_off, Bp, pcp, pcp * Bp, false, s);
@@ -921,7 +921,7 @@ zp_status zp_series_bwd2(const int32_t *h_n, const int32_t *h_m, int64_t M, cons
             g.ct = ct;
             g.a = Operand{ws + L.d_off, pcp, Mp * pcp, zlay_of(ct)}; // A(i=q, k=p) = D[q][p]
             if (ct == CT_BF3)
-                g.b = Operand{ws + L.gt_off, pcp, Bp * pcp, LAY_KC};
+                g.b = Operand{ws + L.gt_off, Bp / 16, Bp * pcp, LAY_FRAG};
             else
                 g.b = Operand{gbuf, Bp, pcp * Bp, LAY_XC};
             g.M = M;

@@ -85,19 +85,13 @@ zp_status series_fwd_run(const Plan &plan, int64_t M, const double *d_r, const d
 zp_status launch_convert(const double *src, int64_t R, int64_t C, int64_t lds, int ct, void *dst, int64_t ldd,
                          int64_t rows_pad, int64_t sub, bool transpose, hipStream_t s);
 
-// Both layouts from one pass over src [R][C]: dst_n [ldt][ldn] = src and
-// dst_t [ldn][ldt] = src^T, zero padded (ldt >= R, ldn >= C, multiples of 64).
-zp_status launch_convert_both(const double *src, int64_t R, int64_t C, int64_t lds, int ct, void *dst_n, int64_t ldn,
-                              int64_t sub_n, void *dst_t, int64_t ldt, int64_t sub_t, hipStream_t s);
-
-// dst[c][e] = src[perm[e]][c] (e < R, zero padded) for columns e < ncols of
-// dst [rows_pad][ldd] (ncols a multiple of 32, <= ldd).
 // bf16 x 3 operand in MFMA fragment order for B(k = e, j = x) = src[perm[e]][x]:
 // per k step of 32 and block of 16 columns, 64 lanes x 8 bf16 contiguous (lane
 // = 16 (k % 32 / 8) + x % 16), blocks along x fastest (xblocks = xpad / 16);
 // three planes sub apart; zero outside R x C.
 zp_status launch_convert_gather_frag(const double *src, const int32_t *perm, int64_t R, int64_t C, int64_t lds,
                                      void *dst, int64_t xpad, int64_t kpad, int64_t sub, hipStream_t s);
+
 // The upstream gradient g [R][C] (rows = points) as the backward's bf16 x 3
 // operands from one read: [xpad_r][xpad_c] k-contiguous into dst_c (the
 // column-dot's B(k = set, j = point)) and, if dst_s is set, MFMA fragment
@@ -105,10 +99,6 @@ zp_status launch_convert_gather_frag(const double *src, const int32_t *perm, int
 // the padded point and set counts (multiples of 32 and 64).
 zp_status launch_convert_g_bwd(const double *src, int64_t R, int64_t C, int64_t lds, void *dst_c, int64_t subc,
                                void *dst_s, int64_t subs, int64_t xpad_r, int64_t xpad_c, hipStream_t s);
-zp_status launch_convert_gather_t(const double *src, const int32_t *perm, int64_t R, int64_t C, int64_t lds,
-                                  int ct, void *dst, int64_t ldd, int64_t rows_pad, int64_t sub, int64_t ncols,
-                                  hipStream_t s);
-
 // Zero the pad (modes >= M, points >= P) of a k-blocked bf16 operand.
 zp_status launch_zero_kb8(void *dst, int64_t M, int64_t Mp, int64_t P, int64_t ld, int64_t sub, hipStream_t s);
 
