@@ -211,7 +211,6 @@ hipStream_t helper_stream()
     return streams[dev];
 }
 
-
 // Forward pipeline: chunks of points alternate between the caller's stream
 // and the helper stream; chunk i+1's basis starts when chunk i's basis has
 // finished, so it runs under chunk i's contraction.  A chunk's contraction
@@ -557,7 +556,8 @@ zp_status zp_series_bwd(const int32_t *h_n, const int32_t *h_m, int64_t M, const
             ldz = pcp;
             zsub = Mp * pcp;
         }
-        // g rows of this chunk: [pcp][Bp] (and [Bp][pcp] for bf16's grad_c operand).
+        // g rows of this chunk: [pcp][Bp] (and MFMA fragment order for bf16's
+        // grad_c operand).
         // In FP64, with B and the chunk already multiples of the pad, g itself
         // has that layout and is read in place.
         const bool g_in_place = ct == CT_F64 && B == Bp && pc == pcp && ((uintptr_t)d_g & 15) == 0;
